@@ -1,0 +1,95 @@
+"""Phase x instance expansion (oracle; test infrastructure only).
+
+A Process that acts on an aerosol phase is applied identically to every instance of that
+phase (Sect. 2.2.3 and Sect. 2.4.2: the Process operates on each instance as determined
+by the aerosol scheme). Gas-phase Processes apply once. Phase transfer
+(HenrysLawPhaseTransfer, SimpolPhaseTransfer) becomes, per instance, a condensation
+reaction G -> A and an evaporation reaction A -> G.
+
+State layout: gas species in input order; then for each phase, for each instance, the
+phase's species in the order the phase lists them.
+"""
+from dataclasses import dataclass
+from typing import List
+
+ARRHENIUS, PHOTOLYSIS, EMISSION, LOSS, CONDENSED, HENRY, SIMPOL = 1, 2, 3, 4, 5, 6, 7
+
+# kind of rate constant an expanded reaction carries
+K_ARRHENIUS, K_PHOTOLYSIS, K_EMISSION, K_LOSS, K_CONDENSED = 1, 2, 3, 4, 5
+K_HENRY_COND, K_HENRY_EVAP, K_SIMPOL_COND, K_SIMPOL_EVAP = 6, 7, 8, 9
+
+
+@dataclass
+class XReaction:
+    kind: int
+    src: int           # input reaction index
+    inst: int          # global phase-instance index, -1 for gas
+    react: List[int]   # state indices (repeats allowed)
+    prod: List[int]
+    yields: List[float]
+    ext: int = -1      # index among externally-settable reactions, else -1
+
+
+@dataclass
+class Expanded:
+    n_state: int
+    n_gas: int
+    gas_state: dict            # species id -> state index (gas)
+    inst_base: List[int]       # global instance -> first state index of its block
+    inst_phase: List[int]      # global instance -> phase index
+    rxns: List[XReaction]
+
+
+def expand(mech) -> Expanded:
+    gas_state = {}
+    for sid, s in enumerate(mech.species):
+        if s.phase < 0:
+            gas_state[sid] = len(gas_state)
+    n_gas = len(gas_state)
+    inst_base, inst_phase = [], []
+    first_inst = []
+    pos = n_gas
+    for p, ph in enumerate(mech.phases):
+        first_inst.append(len(inst_base))
+        for _ in range(ph.n_instances):
+            inst_base.append(pos)
+            inst_phase.append(p)
+            pos += len(ph.species)
+    n_state = pos
+
+    def cond_index(p, inst_local, sid):
+        ph = mech.phases[p]
+        return inst_base[first_inst[p] + inst_local] + ph.species.index(sid)
+
+    rxns = []
+    n_ext = 0
+    for ri, r in enumerate(mech.reactions):
+        t = r.type
+        if t in (ARRHENIUS, PHOTOLYSIS, EMISSION, LOSS):
+            kind = {ARRHENIUS: K_ARRHENIUS, PHOTOLYSIS: K_PHOTOLYSIS,
+                    EMISSION: K_EMISSION, LOSS: K_LOSS}[t]
+            ext = -1
+            if t != ARRHENIUS:
+                ext = n_ext
+                n_ext += 1
+            rxns.append(XReaction(kind, ri, -1, [gas_state[s] for s in r.react],
+                                  [gas_state[s] for s in r.prod], list(r.yields), ext))
+        elif t == CONDENSED:
+            p = r.phase
+            for i in range(mech.phases[p].n_instances):
+                g = first_inst[p] + i
+                rxns.append(XReaction(K_CONDENSED, ri, g,
+                                      [cond_index(p, i, s) for s in r.react],
+                                      [cond_index(p, i, s) for s in r.prod], list(r.yields)))
+        elif t in (HENRY, SIMPOL):
+            p = r.phase
+            gas = gas_state[r.react[0]]
+            kc, ke = (K_HENRY_COND, K_HENRY_EVAP) if t == HENRY else (K_SIMPOL_COND, K_SIMPOL_EVAP)
+            for i in range(mech.phases[p].n_instances):
+                g = first_inst[p] + i
+                aer = cond_index(p, i, r.prod[0])
+                rxns.append(XReaction(kc, ri, g, [gas], [aer], [1.0]))
+                rxns.append(XReaction(ke, ri, g, [aer], [gas], [1.0]))
+        else:
+            raise ValueError(f"unknown reaction type {t}")
+    return Expanded(n_state, n_gas, gas_state, inst_base, inst_phase, rxns)

@@ -1,0 +1,62 @@
+"""Forcing f(y) and its analytic Jacobian (oracle; test infrastructure only).
+
+The forcing of species i is the sum over processes of each process's contribution, and
+the Jacobian entry (i, j) is the sum of the processes' partial derivatives (Sect. 2.4.2,
+the two sums over processes k). Every expanded reaction here is generalized mass action:
+its rate is r = k * prod_{occurrences o} y_{j_o}; it removes one unit of each reactant
+occurrence and adds ``yield`` units of each product. Hence
+
+    f = S r,        S[i, k] = sum(yields of i in k) - (occurrences of i among reactants of k)
+    J = S (dr/dy),  dr_k/dy_j = k_k * sum over occurrences o of j of prod_{o' != o} y_{j_o'}
+
+Both are computed densely; the arithmetic works for complex y so that the Jacobian can
+be checked by the complex-step derivative.
+"""
+import numpy as np
+
+
+class DenseSystem:
+    """Dense S, reactant index table and f/J evaluation for one expanded mechanism."""
+
+    def __init__(self, x):
+        n, R = x.n_state, len(x.rxns)
+        self.n = n
+        S = np.zeros((n, R))
+        react = np.full((R, 3), n, dtype=np.int64)   # index n points at a constant 1
+        for k, xr in enumerate(x.rxns):
+            for o, j in enumerate(xr.react):
+                react[k, o] = j
+                S[j, k] -= 1.0
+            for i, yl in zip(xr.prod, xr.yields):
+                S[i, k] += yl
+        self.S = S
+        self.react = react
+        # Jacobian contributions: for reaction k, reactant occurrence o (species j) and every
+        # species i with S[i, k] != 0, J[i, j] += S[i, k] * dr_k/dy_j(occurrence o).
+        ii, jj, kk, oo, cc = [], [], [], [], []
+        for k, xr in enumerate(x.rxns):
+            members = np.nonzero(S[:, k])[0]
+            for o, j in enumerate(xr.react):
+                for i in members:
+                    ii.append(i); jj.append(j); kk.append(k); oo.append(o); cc.append(S[i, k])
+        self.jc = (np.array(ii, dtype=np.int64), np.array(jj, dtype=np.int64),
+                   np.array(kk, dtype=np.int64), np.array(oo, dtype=np.int64), np.array(cc))
+
+    def rates(self, k, y):
+        ye = np.append(y, 1.0)
+        g = ye[self.react]                            # [R, 3]
+        return k * g[:, 0] * g[:, 1] * g[:, 2]
+
+    def f(self, k, y):
+        return self.S @ self.rates(k, y)
+
+    def jac(self, k, y):
+        n = self.n
+        ye = np.append(y, 1.0)
+        g = ye[self.react]
+        # occurrence o: derivative of g0*g1*g2 w.r.t. g_o is the product of the other two
+        others = np.stack([g[:, 1] * g[:, 2], g[:, 0] * g[:, 2], g[:, 0] * g[:, 1]], axis=1)
+        ii, jj, kk, oo, cc = self.jc
+        J = np.zeros((n, n), dtype=np.result_type(y, k))
+        np.add.at(J, (ii, jj), cc * k[kk] * others[kk, oo])
+        return J
