@@ -1,0 +1,189 @@
+"""Benchmark: cell-steps/s of the batched stiff-chemistry solve on one MI355X.
+
+One benchmark step = one host time step (dt = 3600 s) of every cell of the workload: rate
+constants, then variable-order BDF with Newton iteration over the sparse LU, until every
+cell reaches the end of the step. The default workload is the realistic-size gas-phase
+configuration (10,000 cells, 72 species / 233 reactions, diurnal photolysis, FP64,
+rtol 1e-4, atol 1e-12). Inputs are resident in device memory before timing starts; each
+step re-solves the same initial state.
+
+Prints one JSON line. Extra fields: the plain per-cell GPU BDF rate at the same tolerance
+(`plain_value`, `speedup_vs_plain`), the accuracy of both forms against the oracle on
+sampled cells, the roofline of the dominant kernel and the CPU-oracle baseline.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+FP64_VECTOR_PEAK_TFLOPS = 78.6     # MI355X FP64 vector (256 CU x 2.4 GHz x 128 flop/clk)
+HBM_PEAK_GBS = 8000.0
+
+WORKLOADS = {
+    "c2": "gas-phase realistic size: 10,000 cells, 72 species / 233 reactions, 1 x 3600 s",
+    "c1": "plain box model: 100 cells, 20 species / 40 reactions, 60 x 60 s",
+    "c3": "multiphase: 100,000 cells, 72 gas + 6 phases x 4 sections (192 state / 809 reactions), 1 x 3600 s",
+    "c5": "large: 500,000 cells, 200 gas + 10 phases x 8 sections (520 state / 1720 reactions), 1 x 3600 s",
+}
+
+
+def algorithmic_flops(info, mech, stats_mean):
+    """FP64 flops one cell's solve needs, from its counters (see the flop table in the design doc)."""
+    N, Z = info["n_state"], info["nnz_fill"]
+    sum_nr_nr1 = 0
+    for r in mech.reactions:
+        nr = len(r.react)
+        mult = 1
+        if r.phase >= 0 and r.type == 5:
+            mult = mech.phases[r.phase].n_instances
+        elif r.type in (6, 7):
+            mult = 2 * mech.phases[r.phase].n_instances
+            nr = 1
+        sum_nr_nr1 += mult * nr * (nr - 1)
+    f_flops = info["n_partials"] + 2 * info["n_terms"]
+    j_flops = sum_nr_nr1 + 2 * info["n_jac_contrib"] + 2 * Z
+    lu_flops = 2 * info["lu_pairs"] + (Z - N) // 2
+    solve_flops = 2 * (Z - N) + N
+    s = stats_mean
+    return (s["n_f"] * f_flops + s["n_jac"] * j_flops + s["n_lu"] * lu_flops
+            + s["newton_iters"] * (solve_flops + 8 * N) + s["steps"] * 30 * N)
+
+
+def run_gpu(name, engine, steps, warmup, rtol, atol, n_cells=None):
+    import torch
+
+    from paper_2111_07436_amd import camp
+    from paper_2111_07436_amd import workloads as W
+
+    wl = W.make_workload(name, n_cells=n_cells)
+    m = camp.Mech(wl.mech)
+    denv = camp.DeviceEnv(wl.env)
+    y0 = torch.from_numpy(wl.y0).cuda()
+    y = torch.empty_like(y0)
+    st = torch.empty(wl.n_cells, dtype=torch.int32, device="cuda")
+    opts = camp.make_opts(engine)
+
+    def one_step():
+        for _ in range(wl.n_calls):
+            m.solve_device(denv, y, wl.dt, rtol, atol, opts, d_status=st)
+
+    for _ in range(warmup):
+        y.copy_(y0)
+        one_step()
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    t0 = time.perf_counter()
+    for i in range(steps):
+        y.copy_(y0)
+        ev[i][0].record()
+        one_step()
+        ev[i][1].record()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    kernel_ms = float(np.mean([a.elapsed_time(b) for a, b in ev])) / wl.n_calls
+    failed = camp.count_failed(st)
+    # counters of one extra solve
+    y.copy_(y0)
+    stats = torch.zeros((wl.n_cells, 8), dtype=torch.int32, device="cuda")
+    for _ in range(wl.n_calls):
+        m.solve_device(denv, y, wl.dt, rtol, atol, opts, d_status=st, d_stats=stats)
+    torch.cuda.synchronize()
+    s = stats.cpu().numpy().astype(np.float64)
+    mean = {f: float(s[:, i].mean()) for i, f in enumerate(camp.STATS_FIELDS)}
+    return dict(wl=wl, mech=m, seconds=t1 - t0, kernel_ms=kernel_ms, failed=failed, stats=mean,
+                y=y.cpu().numpy())
+
+
+def accuracy(wl, y_gpu, cells, processes):
+    from oracle.solve import oracle_solve_parallel
+    yr, st = oracle_solve_parallel(wl.mech, wl.env, wl.y0, wl.dt, wl.n_calls, 1e-10, 1e-20, cells, processes)
+    ref = yr[st == 0]
+    got = y_gpu[np.asarray(cells)[st == 0]]
+    big = np.abs(ref) >= 1e-12
+    rel = np.abs(got[big] - ref[big]) / np.abs(ref[big])
+    frac_fail = float(np.mean(rel > 1e-4)) if rel.size else 0.0
+    return {"max_rel": float(rel.max()), "p99_rel": float(np.quantile(rel, 0.99)),
+            "frac_species_over_1e-4": frac_fail, "cells": len(cells), "oracle_rtol": 1e-10}
+
+
+def cpu_baseline(wl, rtol, atol, sample, processes):
+    from oracle.solve import oracle_solve_parallel
+    cells = np.linspace(0, wl.n_cells - 1, sample).astype(int)
+    t = time.perf_counter()
+    _, st = oracle_solve_parallel(wl.mech, wl.env, wl.y0, wl.dt, wl.n_calls, rtol, atol, cells, processes)
+    dt = time.perf_counter() - t
+    return {"value": len(cells) * 1 / dt, "unit": "cell-steps/s", "cores": processes, "kind": "oracle",
+            "sample": f"{len(cells)} cells evenly strided over the {wl.n_cells}-cell workload, "
+                      f"one host step each, rtol {rtol:g}, atol {atol:g}, one process per core",
+            "seconds": dt, "failed": int(np.sum(st != 0))}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS))
+    ap.add_argument("--engine", default="auto")
+    ap.add_argument("--rtol", type=float, default=1e-4)
+    ap.add_argument("--atol", type=float, default=1e-12)
+    ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-accuracy", action="store_true")
+    ap.add_argument("--cpu-sample", type=int, default=1000)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: every cell is independent, so more GPUs shard the cells "
+              "with no exchange (see DESIGN.md); only --gpus 1 is supported in this build.",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+    assert torch.cuda.is_available(), "bench.py needs a HIP device"
+    processes = max(1, min(16, os.cpu_count() or 1))
+
+    main_run = run_gpu(args.workload, args.engine, args.steps, args.warmup, args.rtol, args.atol)
+    wl = main_run["wl"]
+    cells = wl.n_cells
+    value = cells * args.steps / main_run["seconds"]
+    out = {
+        "metric": "cell-steps/sec at rtol 1e-4 vs plain per-cell BDF; served p50/p99 latency",
+        "value": value, "unit": "cell-steps/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": 1e3 * main_run["seconds"] / args.steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic (seeded generator, PCG64 seed 0)",
+        "config": {"workload": WORKLOADS[args.workload], "cells": cells, "dt_s": wl.dt,
+                   "rtol": args.rtol, "atol": args.atol, "engine": args.engine},
+        "failed_cells": main_run["failed"],
+        "cell_stats_mean": main_run["stats"],
+    }
+    if not args.no_plain:
+        plain = run_gpu(args.workload, "plain", 1, 1, args.rtol, args.atol)
+        pv = cells / plain["seconds"]
+        out["plain_value"] = pv
+        out["speedup_vs_plain"] = value / pv
+    flops = algorithmic_flops(main_run["mech"].info, wl.mech, main_run["stats"]) * cells
+    achieved = flops / (main_run["kernel_ms"] * 1e-3) / 1e12
+    compulsory = 8.0 * cells * (2 * wl.mech.n_state + 3) * wl.n_calls
+    out["roofline"] = {"bound": "alu", "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS,
+                       "unit": "TFLOP/s", "frac": achieved / FP64_VECTOR_PEAK_TFLOPS, "traffic": None,
+                       "kernel": "bdf_wave_kernel", "kernel_ms": main_run["kernel_ms"],
+                       "flops_per_launch": flops,
+                       "compulsory_hbm_GBs": compulsory / (main_run["kernel_ms"] * 1e-3) / 1e9}
+    if not args.no_accuracy:
+        sample = list(np.linspace(0, cells - 1, 16).astype(int))
+        out["accuracy"] = accuracy(wl, main_run["y"], sample, processes)
+        if not args.no_plain:
+            out["accuracy_plain"] = accuracy(wl, plain["y"], sample, processes)
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(wl, args.rtol, args.atol, min(args.cpu_sample, cells), processes)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,277 @@
+/*
+ * camp.h -- C ABI of the MI355X-native batched stiff multiphase chemistry solver.
+ *
+ * The operation: every grid cell's gas + aerosol-phase chemistry is an independent stiff
+ * ODE system dy/dt = f(y) over one host time step dt. The host model creates one object
+ * per mechanism, sets externally computed rates, passes temperature, pressure,
+ * concentrations, aerosol state and dt, asks for a solve, and reads the state back
+ * (paper Sect. 2.1 CampCore; Sect. 2.4.2 runtime workflow). Each cell is integrated with
+ * variable-order BDF and Newton iteration over a sparse LU (Sect. 2.4.1). Here all cells
+ * of a call are solved together on one GPU.
+ *
+ * Conventions
+ *  - Every function returns camp_status (0 = OK, < 0 = error). No exception crosses the
+ *    ABI. On error, camp_last_error() returns a thread-local message.
+ *  - Concentrations are mol m^-3 of air. Arrays of per-cell data are row-major
+ *    [cells][...] (one cell's values contiguous), double precision.
+ *  - "host" pointers are ordinary CPU memory; "device" pointers are HIP device memory
+ *    (e.g. torch.Tensor.data_ptr() of a CUDA tensor). Streams are hipStream_t passed as
+ *    void* (NULL = the default stream).
+ *  - The library never frees or retains caller memory after a call returns (the device
+ *    calls are stream-ordered: inputs must stay valid until the stream reaches the call).
+ *
+ * State layout (n_state values per cell): gas species in the order given to
+ * camp_mech_load, then for each phase in order, for each of its instances in order, the
+ * phase's species in the order the phase lists them (paper Sect. 2.2.3: a phase's
+ * species and chemistry are identical in every instance).
+ */
+#ifndef CAMP_H
+#define CAMP_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  CAMP_OK = 0,
+  CAMP_EINVAL = -1,   /* invalid argument or mechanism description               */
+  CAMP_ENOMEM = -2,   /* host or device allocation failed                         */
+  CAMP_EDEVICE = -3,  /* HIP runtime error or no usable device                    */
+  CAMP_ESOLVE = -4    /* at least one cell failed; see the per-cell status array  */
+} camp_status;
+
+/* Per-cell status codes written by the solve calls. A failed cell's state is restored
+ * to its input values. */
+enum {
+  CAMP_CELL_OK = 0,
+  CAMP_CELL_MAX_STEPS = 1,    /* more step attempts than opts.max_steps            */
+  CAMP_CELL_H_MIN = 2,        /* step size fell below opts.h_min                   */
+  CAMP_CELL_ERR_FAIL = 3,     /* 10 consecutive local error test failures          */
+  CAMP_CELL_NEWTON_FAIL = 4,  /* 10 consecutive Newton convergence failures        */
+  CAMP_CELL_NONFINITE = 5     /* non-finite rate constant, forcing or weight       */
+};
+
+/* Process types (paper Sect. 2.2.1, table of Process-extending classes).
+ * p[] meanings:
+ *  ARRHENIUS            gas. k = A exp(-Ea/(kb T)) (T/D)^B (1 + E P).
+ *                       p = {A [(molecule cm^-3)^-(n_r-1) s^-1], Ea/kb [K], B, D [K], E [Pa^-1]}.
+ *  PHOTOLYSIS           gas, 1 reactant. p = {J0 [s^-1], sza_flag}. sza_flag != 0 scales
+ *                       J0 by max(0, cos sza) of the cell. Externally settable.
+ *  EMISSION             gas, 0 reactants, 1 product. p = {E [mol m^-3 s^-1]}. Settable.
+ *  FIRST_ORDER_LOSS     gas, 1 reactant, 0 products. p = {k [s^-1]}. Settable.
+ *  CONDENSED_ARRHENIUS  reactants/products in .phase, applied in every instance.
+ *                       p = {A, Ea/kb, B, D, E, aqueous}. aqueous != 0: k in M^-(n_r-1) s^-1
+ *                       acting on molarities (phase volume = mass / density); else in
+ *                       (mol m^-3 air)^-(n_r-1) s^-1.
+ *  HENRY_TRANSFER       react[0] gas species G, prod[0] species A of .phase.
+ *                       p = {H298 [M Pa^-1], C [K]}; H(T) = H298 exp(C (1/T - 1/298)).
+ *                       Condensation k_c = 4 pi r D_g f_FS(Kn, alpha) N (Fuchs-Sutugin);
+ *                       evaporation k_c / (H 1000 V R T).
+ *  SIMPOL_TRANSFER      as HENRY_TRANSFER; p = {B1, B2, B3, B4}, log10 p0[atm] =
+ *                       B1/T + B2 + B3 T + B4 ln T; evaporation k_c p0 101325 / (R T n_abs),
+ *                       n_abs = mass / mw_absorber of the instance.
+ * A phase instance with zero mass has all its rate constants equal to 0.
+ */
+enum {
+  CAMP_RXN_ARRHENIUS = 1,
+  CAMP_RXN_PHOTOLYSIS = 2,
+  CAMP_RXN_EMISSION = 3,
+  CAMP_RXN_FIRST_ORDER_LOSS = 4,
+  CAMP_RXN_CONDENSED_ARRHENIUS = 5,
+  CAMP_RXN_HENRY_TRANSFER = 6,
+  CAMP_RXN_SIMPOL_TRANSFER = 7
+};
+
+typedef struct {
+  const char* name;      /* may be NULL                                              */
+  int phase;             /* -1 gas, else index into the phase array                  */
+  double mw_kg_mol;      /* gas species: molecular weight (used by phase transfer)   */
+  double diff_m2_s;      /* gas species: gas-phase diffusion coefficient             */
+  double accom;          /* gas species: mass accommodation coefficient              */
+} camp_species;
+
+typedef struct {
+  const char* name;       /* may be NULL                                             */
+  int n_species;          /* >= 1                                                    */
+  const int* species;     /* [n_species] species ids, each with .phase == this index */
+  int n_instances;        /* >= 1 (modes, sections or particles)                     */
+  double density_kg_m3;   /* > 0                                                     */
+  double mw_absorber_kg_mol; /* > 0, SIMPOL absorbing-mass molar mass                */
+} camp_phase;
+
+typedef struct {
+  int type;               /* CAMP_RXN_*                                              */
+  int phase;              /* condensed/transfer: phase index; gas: ignored           */
+  int n_react;            /* 0..3 (repeats allowed: 2A -> B lists A twice)           */
+  int react[3];           /* species ids                                             */
+  int n_prod;             /* 0..3, distinct                                          */
+  int prod[3];
+  double yield[3];        /* molar yields of the products                            */
+  double p[6];            /* type-specific parameters, see above                     */
+} camp_reaction;
+
+typedef struct camp_mech camp_mech;
+
+/* Compile a mechanism: validate it, expand phases over instances, assign state ids, take
+ * the union of the Jacobian elements every process touches plus the diagonal (paper
+ * table of Process functions: get_used_jacobian_elements, update_ids), choose a
+ * fill-reducing elimination order, compute the LU fill symbolically once, and build the
+ * level-scheduled elimination and solve tables. All inputs are deep-copied; the caller
+ * may free them on return. Host-only work: no device is touched until the first solve.
+ * Errors: CAMP_EINVAL (bad ids, counts, non-finite or negative parameters, transfer
+ * partner not gas-phase, phase without species or instances), CAMP_ENOMEM. */
+int camp_mech_load(const camp_reaction* rxns, int n_rxn, const camp_species* species,
+                   int n_species, const camp_phase* phases, int n_phases, camp_mech** out);
+
+typedef struct {
+  int n_state;          /* N: state values per cell                                  */
+  int n_gas;
+  int n_instances;      /* total phase instances                                     */
+  int n_rxn_expanded;   /* R: generalized mass-action reactions after expansion      */
+  int n_external;       /* externally settable processes (rate_override columns)     */
+  int nnz_pattern;      /* Jacobian pattern incl. diagonal, before fill              */
+  int nnz_fill;         /* Z: LU pattern after fill                                  */
+  long long lu_pairs;   /* U: multiply-subtract pairs of one LU factorization        */
+  int lu_levels;        /* dependency levels of the factorization                    */
+  int fwd_levels;       /* dependency levels of the forward solve                    */
+  int bwd_levels;       /* dependency levels of the backward solve                   */
+  int n_partials;       /* sum over reactions of reactant occurrences                */
+  int n_terms;          /* forcing terms (species x reaction with nonzero net coef)  */
+  int n_jac_contrib;    /* Jacobian contributions                                    */
+} camp_mech_info_t;
+
+int camp_mech_info(const camp_mech* mech, camp_mech_info_t* info);
+
+/* Export the compiled structure (for validation). Any pointer may be NULL.
+ *  perm[N]       : elimination position t holds state index perm[t]
+ *  row_ptr[N+1], col[Z] : filled pattern, CSR in elimination order (cols in elimination
+ *                  order, ascending); value slot s of the device matrices is CSR entry s.
+ *  pattern0[Z]   : 1 if the slot is in the unfilled pattern, 0 if it is fill. */
+int camp_mech_export(const camp_mech* mech, int* perm, int* row_ptr, int* col, int* pattern0);
+
+void camp_mech_free(camp_mech* mech);
+
+/* Per-cell environment. All arrays [cells] or [cells][n_instances] row-major.
+ * radius_m / aer_mass_kg_m3 may be NULL when the mechanism has no phases.
+ * cos_sza may be NULL (treated as 1). rate_override may be NULL; else [cells][n_external]
+ * values that replace the configured rates of the photolysis, emission and loss
+ * processes, in the order those processes appear in the reaction array (paper Sect. 2.4.2:
+ * Process-connection objects). */
+typedef struct {
+  const double* T_K;
+  const double* P_Pa;
+  const double* cos_sza;
+  const double* radius_m;
+  const double* aer_mass_kg_m3;
+  const double* rate_override;
+} camp_env;
+
+/* Solver engines. */
+enum {
+  CAMP_ENGINE_AUTO = 0,          /* the autotuner's choice for (mechanism, cell count)  */
+  CAMP_ENGINE_PLAIN = 1,         /* one lane per cell, separate kernels per BDF phase   */
+  CAMP_ENGINE_FUSED_WAVE = 2,    /* persistent fused kernel, one wavefront per cell,    */
+                                 /* matrix and vectors resident in LDS                  */
+  CAMP_ENGINE_FUSED_LANE = 3     /* persistent fused kernel, one lane per cell,         */
+                                 /* cell-interleaved matrices streamed from HBM         */
+};
+
+typedef struct {
+  int max_order;        /* 1..5 (default 5)                                           */
+  int max_steps;        /* step attempts per cell per call (default 100000)           */
+  int newton_max_iter;  /* default 4                                                  */
+  double h_min;         /* absolute minimum step, s (default 1e-14 * dt)              */
+  double h_init;        /* > 0: initial step, s (default: starting-step heuristic)    */
+  int engine;           /* CAMP_ENGINE_*                                              */
+  int wg_per_cu;        /* FUSED_WAVE persistent grid: workgroups per CU, 0 = auto     */
+  int persistent;       /* FUSED_*: 1 = persistent grid with a cell queue, 0 = one    */
+                        /* workgroup per cell batch, -1 = auto                        */
+  int use_graph;        /* 1 = replay a captured hipGraph of the call's launches      */
+} camp_opts;
+
+/* Per-cell counters (optional output). */
+typedef struct {
+  int steps, rejected, newton_fail, newton_iters, n_f, n_jac, n_lu, order;
+} camp_cell_stats;
+
+/* Solve n_cells cells with host arrays. state[cells][n_state] is read and overwritten in
+ * place. cell_status[cells] and cell_stats[cells] may be NULL. opts may be NULL.
+ * Returns CAMP_ESOLVE if any cell failed (its row is left at its input values). */
+int camp_solve(camp_mech* mech, int n_cells, double* state, const camp_env* env, double dt,
+               double rtol, double atol, const camp_opts* opts, int* cell_status,
+               camp_cell_stats* cell_stats);
+
+/* Same with device arrays (env fields are device pointers) on a stream. Stream-ordered:
+ * results are ready when the stream reaches the end of the call. cell_status is required
+ * (device, [cells]). The return value reports argument and launch errors only; per-cell
+ * failures are reported through cell_status (use camp_count_failed). */
+int camp_solve_device(camp_mech* mech, int n_cells, double* d_state, const camp_env* d_env,
+                      double dt, double rtol, double atol, const camp_opts* opts,
+                      int* d_cell_status, camp_cell_stats* d_cell_stats, void* stream);
+
+/* --- Individual hot-path steps on device arrays (validation and composition). All
+ *     per-cell arrays are row-major [cells][...] device memory. --- */
+
+/* Rate constants k[cells][R] in expanded-reaction order (camp_mech_info.n_rxn_expanded).
+ * Expansion order: processes in input order; a gas process gives one reaction; a
+ * condensed-phase process one per instance of its phase; a transfer process two per
+ * instance (condensation G -> A, then evaporation A -> G). */
+int camp_rate_constants_device(camp_mech* mech, int n_cells, const camp_env* d_env,
+                               double* d_k, void* stream);
+
+/* Forcing f[cells][N] = sum over reactions of net stoichiometry times
+ * k * product of reactant concentrations (paper Sect. 2.4.2), state layout as above. */
+int camp_forcing_device(camp_mech* mech, int n_cells, const double* d_k, const double* d_y,
+                        double* d_f, void* stream);
+
+/* Newton matrix M = I - gamma * J(y) in the filled pattern: m[cells][Z], slot order of
+ * camp_mech_export (fill slots hold 0 off the diagonal). */
+int camp_newton_matrix_device(camp_mech* mech, int n_cells, const double* d_k,
+                              const double* d_y, double gamma, double* d_m, void* stream);
+
+/* In-place LU factorization of m[cells][Z] (static order, no pivoting): afterwards the
+ * strictly lower slots hold L (unit diagonal implied) and the rest U. */
+int camp_lu_factor_device(camp_mech* mech, int n_cells, double* d_m, void* stream);
+
+/* Solve (L U) x = b for each cell; b[cells][N] in state layout is overwritten by x. */
+int camp_lu_solve_device(camp_mech* mech, int n_cells, const double* d_lu, double* d_b,
+                         void* stream);
+
+/* Number of cells with nonzero status (device status array), written to *n_failed. */
+int camp_count_failed(int n_cells, const int* d_cell_status, int* n_failed, void* stream);
+
+/* --- Serving: requests are admitted by device-memory footprint and run concurrently on
+ *     the device; each request's cells are solved exactly as by camp_solve_device. --- */
+typedef struct camp_server camp_server;
+
+/* max_bytes: budget of device memory for in-flight requests (0 = 50% of free memory).
+ * max_inflight: concurrent requests (streams), 1..64. */
+int camp_serve_create(long long max_bytes, int max_inflight, camp_server** out);
+
+/* Submit a request on device-resident data (pointers stay owned by the caller and must
+ * remain valid until the request completes). The request is queued if it does not fit
+ * the memory budget. Returns a ticket (> 0). */
+int camp_serve_submit(camp_server* srv, camp_mech* mech, int n_cells, double* d_state,
+                      const camp_env* d_env, double dt, double rtol, double atol,
+                      const camp_opts* opts, int* d_cell_status, long long* ticket);
+
+/* Poll: *done = 1 when finished; then *n_failed is its failed-cell count and
+ * *latency_s the time from submission to completion. */
+int camp_serve_poll(camp_server* srv, long long ticket, int* done, int* n_failed,
+                    double* latency_s);
+
+/* Block until the request completes. */
+int camp_serve_wait(camp_server* srv, long long ticket);
+
+/* Admit queued requests whose footprint now fits and retire finished ones; returns the
+ * number of requests in flight in *inflight and queued in *queued. */
+int camp_serve_progress(camp_server* srv, int* inflight, int* queued);
+
+void camp_serve_destroy(camp_server* srv);
+
+const char* camp_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CAMP_H */

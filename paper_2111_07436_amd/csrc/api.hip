@@ -1,0 +1,507 @@
+// C ABI: mechanism lifecycle, device residency, solve dispatch, single-step entry points.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "camp.h"
+#include "runtime.hpp"
+
+namespace camp {
+
+namespace {
+thread_local std::string g_err;
+
+size_t align256(size_t v) { return (v + 255) / 256 * 256; }
+
+// Copies every table of the compiled mechanism into one device allocation.
+int upload(camp_mech* mh, int device, DeviceTables& out) {
+  const Compiled& C = mh->C;
+  struct Item {
+    const void* src;
+    size_t bytes;
+    size_t off;
+  };
+  std::vector<Item> items;
+  size_t total = 0;
+  auto add = [&](const void* src, size_t bytes) {
+    items.push_back({src, bytes, total});
+    size_t off = total;
+    total = align256(total + std::max<size_t>(bytes, 1));
+    return off;
+  };
+  const int R = C.n_rxn;
+  std::vector<int> kind(R), ext(R), inst(R), nr(R);
+  std::vector<double> v((size_t)R * kRateParams);
+  for (int k = 0; k < R; ++k) {
+    kind[k] = C.rate[k].kind;
+    ext[k] = C.rate[k].ext;
+    inst[k] = C.rate[k].inst;
+    nr[k] = C.rate[k].nr;
+    for (int j = 0; j < kRateParams; ++j) v[(size_t)k * kRateParams + j] = C.rate[k].v[j];
+  }
+  std::vector<uint8_t> is_diag(C.nnz, 0);
+  for (int t = 0; t < C.n_state; ++t) is_diag[C.diag[t]] = 1;
+  auto pairs = [](const std::vector<int>& a, const std::vector<int>& b) {
+    std::vector<int> p(2 * a.size());
+    for (size_t i = 0; i < a.size(); ++i) {
+      p[2 * i] = a[i];
+      p[2 * i + 1] = b[i];
+    }
+    return p;
+  };
+  std::vector<int> lup = pairs(C.lu_pa, C.lu_pb), fwp = pairs(C.fwd_pa, C.fwd_pb),
+                   bwp = pairs(C.bwd_pa, C.bwd_pb);
+  static_assert(sizeof(Task) == sizeof(DTask), "task layout");
+
+  size_t o_kind = add(kind.data(), 4 * R), o_ext = add(ext.data(), 4 * R), o_inst = add(inst.data(), 4 * R),
+         o_nr = add(nr.data(), 4 * R), o_v = add(v.data(), 8 * v.size()),
+         o_react = add(C.rx_react.data(), 4 * C.rx_react.size()),
+         o_pofs = add(C.rx_pofs.data(), 4 * C.rx_pofs.size()),
+         o_tptr = add(C.term_ptr.data(), 4 * C.term_ptr.size()),
+         o_trxn = add(C.term_rxn.data(), 4 * C.term_rxn.size()),
+         o_tcoef = add(C.term_coef.data(), 8 * C.term_coef.size()),
+         o_jptr = add(C.jc_ptr.data(), 4 * C.jc_ptr.size()),
+         o_jpart = add(C.jc_part.data(), 4 * C.jc_part.size()),
+         o_jcoef = add(C.jc_coef.data(), 8 * C.jc_coef.size()),
+         o_isd = add(is_diag.data(), is_diag.size()), o_diag = add(C.diag.data(), 4 * C.diag.size()),
+         o_perm = add(C.perm.data(), 4 * C.perm.size()),
+         o_lut = add(C.lu_tasks.data(), sizeof(Task) * C.lu_tasks.size()),
+         o_fwt = add(C.fwd_tasks.data(), sizeof(Task) * C.fwd_tasks.size()),
+         o_bwt = add(C.bwd_tasks.data(), sizeof(Task) * C.bwd_tasks.size()),
+         o_lup = add(lup.data(), 4 * lup.size()), o_fwp = add(fwp.data(), 4 * fwp.size()),
+         o_bwp = add(bwp.data(), 4 * bwp.size()),
+         o_wlu = add(mh->wlu.tasks.data(), sizeof(Task) * mh->wlu.tasks.size()),
+         o_wlulp = add(mh->wlu.level_pass.data(), 4 * mh->wlu.level_pass.size()),
+         o_wfw = add(mh->wfwd.tasks.data(), sizeof(Task) * mh->wfwd.tasks.size()),
+         o_wfwlp = add(mh->wfwd.level_pass.data(), 4 * mh->wfwd.level_pass.size()),
+         o_wbw = add(mh->wbwd.tasks.data(), sizeof(Task) * mh->wbwd.tasks.size()),
+         o_wbwlp = add(mh->wbwd.level_pass.data(), 4 * mh->wbwd.level_pass.size());
+
+  std::vector<char> host(total, 0);
+  for (auto& it : items)
+    if (it.bytes) std::memcpy(host.data() + it.off, it.src, it.bytes);
+  void* blob = nullptr;
+  hipError_t e = hipMalloc(&blob, total);
+  if (e != hipSuccess) return hip_fail(e, "hipMalloc(mechanism tables)");
+  e = hipMemcpy(blob, host.data(), total, hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    hipFree(blob);
+    return hip_fail(e, "hipMemcpy(mechanism tables)");
+  }
+  char* b = static_cast<char*>(blob);
+  DevMech& d = out.dm;
+  d.N = C.n_state;
+  d.R = R;
+  d.Z = C.nnz;
+  d.n_inst = C.n_inst;
+  d.n_ext = C.n_ext;
+  d.n_part = C.n_partials;
+  d.n_gas = C.n_gas;
+  d.lu_levels = C.lu_levels();
+  d.fwd_levels = C.fwd_levels();
+  d.bwd_levels = C.bwd_levels();
+  d.rs_kind = (const int*)(b + o_kind);
+  d.rs_ext = (const int*)(b + o_ext);
+  d.rs_inst = (const int*)(b + o_inst);
+  d.rs_nr = (const int*)(b + o_nr);
+  d.rs_v = (const double*)(b + o_v);
+  d.rx_react = (const int*)(b + o_react);
+  d.rx_pofs = (const int*)(b + o_pofs);
+  d.term_ptr = (const int*)(b + o_tptr);
+  d.term_rxn = (const int*)(b + o_trxn);
+  d.term_coef = (const double*)(b + o_tcoef);
+  d.jc_ptr = (const int*)(b + o_jptr);
+  d.jc_part = (const int*)(b + o_jpart);
+  d.jc_coef = (const double*)(b + o_jcoef);
+  d.is_diag = (const uint8_t*)(b + o_isd);
+  d.diag = (const int*)(b + o_diag);
+  d.perm = (const int*)(b + o_perm);
+  d.lu_task = (const DTask*)(b + o_lut);
+  d.n_lu_task = (int)C.lu_tasks.size();
+  d.fwd_task = (const DTask*)(b + o_fwt);
+  d.n_fwd_task = (int)C.fwd_tasks.size();
+  d.bwd_task = (const DTask*)(b + o_bwt);
+  d.n_bwd_task = (int)C.bwd_tasks.size();
+  d.lu_pair = (const int2*)(b + o_lup);
+  d.fwd_pair = (const int2*)(b + o_fwp);
+  d.bwd_pair = (const int2*)(b + o_bwp);
+  d.wlu = (const DTask*)(b + o_wlu);
+  d.wlu_lp = (const int*)(b + o_wlulp);
+  d.wfwd = (const DTask*)(b + o_wfw);
+  d.wfwd_lp = (const int*)(b + o_wfwlp);
+  d.wbwd = (const DTask*)(b + o_wbw);
+  d.wbwd_lp = (const int*)(b + o_wbwlp);
+  out.device = device;
+  out.blob = blob;
+  out.bytes = total;
+  return CAMP_OK;
+}
+
+// Device-resident tables of `mh` for the current device (uploaded on first use).
+int resident(camp_mech* mh, const DevMech** dm) {
+  int device = 0;
+  hipError_t e = hipGetDevice(&device);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  std::lock_guard<std::mutex> g(mh->mu);
+  auto it = mh->dev.find(device);
+  if (it == mh->dev.end()) {
+    DeviceTables t;
+    int rc = upload(mh, device, t);
+    if (rc != CAMP_OK) return rc;
+    it = mh->dev.emplace(device, t).first;
+  }
+  *dm = &it->second.dm;
+  return CAMP_OK;
+}
+
+int check_solve_args(camp_mech* mh, int n_cells, const void* state, const camp_env* env,
+                     double dt, double rtol, double atol) {
+  if (!mh) { set_error("mechanism is NULL"); return CAMP_EINVAL; }
+  if (n_cells < 0) { set_error("n_cells < 0"); return CAMP_EINVAL; }
+  if (n_cells > 0 && (!state || !env || !env->T_K || !env->P_Pa)) {
+    set_error("state, env, env->T_K and env->P_Pa are required");
+    return CAMP_EINVAL;
+  }
+  if (n_cells > 0 && mh->C.n_inst > 0 && (!env->radius_m || !env->aer_mass_kg_m3)) {
+    set_error("mechanism has aerosol phases: env->radius_m and env->aer_mass_kg_m3 are required");
+    return CAMP_EINVAL;
+  }
+  if (!(dt > 0) || !std::isfinite(dt)) { set_error("dt must be positive and finite"); return CAMP_EINVAL; }
+  if (!(rtol > 0) || !std::isfinite(rtol)) { set_error("rtol must be positive and finite"); return CAMP_EINVAL; }
+  if (!(atol >= 0) || !std::isfinite(atol)) { set_error("atol must be >= 0 and finite"); return CAMP_EINVAL; }
+  return CAMP_OK;
+}
+
+SolveParams make_params(double dt, double rtol, double atol, const camp_opts* o) {
+  SolveParams sp;
+  sp.dt = dt;
+  sp.rtol = rtol;
+  sp.atol = atol;
+  sp.max_order = (o && o->max_order >= 1 && o->max_order <= kMaxOrder) ? o->max_order : kMaxOrder;
+  sp.max_steps = (o && o->max_steps > 0) ? o->max_steps : 100000;
+  sp.newton_maxit = (o && o->newton_max_iter > 0) ? std::min(o->newton_max_iter, 16) : 4;
+  sp.h_min = (o && o->h_min > 0) ? o->h_min : 1e-14 * dt;
+  sp.h_init = (o && o->h_init > 0) ? o->h_init : 0.0;
+  sp.newton_tol = 0.1;
+  return sp;
+}
+
+DevEnv make_env(const camp_env* e) {
+  return DevEnv{e->T_K, e->P_Pa, e->cos_sza, e->radius_m, e->aer_mass_kg_m3, e->rate_override};
+}
+
+int n_cus() {
+  static int cus = 0;
+  if (!cus) {
+    int dev = 0;
+    hipGetDevice(&dev);
+    hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (cus <= 0) cus = 256;
+  }
+  return cus;
+}
+
+}  // namespace
+
+void set_error(const std::string& msg) { g_err = msg; }
+
+int hip_fail(hipError_t e, const char* what) {
+  g_err = std::string(what) + ": " + hipGetErrorString(e);
+  return e == hipErrorOutOfMemory ? CAMP_ENOMEM : CAMP_EDEVICE;
+}
+
+// Dispatch of one device solve with a resolved tuning.
+int solve_device_tuned(camp_mech* mh, const DevMech& dm, int n_cells, double* d_state,
+                       const camp_env* d_env, const SolveParams& sp, const camp_opts* opts,
+                       int* d_status, camp_cell_stats* d_stats, hipStream_t stream, const Tuning& tu) {
+  (void)mh;
+  DevEnv env = make_env(d_env);
+  const int use_graph = opts ? opts->use_graph : 0;
+  hipError_t e = hipSuccess;
+  if (tu.engine == CAMP_ENGINE_PLAIN) {
+    e = run_plain(dm, env, d_state, n_cells, sp, d_status, d_stats, use_graph, stream);
+  } else if (tu.engine == CAMP_ENGINE_FUSED_LANE) {
+    const int slots = std::max(256, n_cus() * 4 * 64 * 2);
+    e = run_fused_lane(dm, env, d_state, n_cells, sp, d_status, d_stats, slots, stream);
+  } else {
+    if ((dm.N + kWave - 1) / kWave > 9) {
+      set_error("wavefront engine supports at most 576 state variables per cell");
+      return CAMP_EINVAL;
+    }
+    if (wave_lds_bytes(dm) > 160 * 1024) {
+      set_error("mechanism does not fit the wavefront engine's LDS budget");
+      return CAMP_EINVAL;
+    }
+    if (tu.persistent) {
+      int* queue = nullptr;
+      e = hipMallocAsync((void**)&queue, 256, stream);
+      if (e != hipSuccess) return hip_fail(e, "hipMallocAsync(queue)");
+      e = launch_fill_int(queue, 1, 0, stream);
+      const int grid = std::min(n_cells, n_cus() * tu.grid_mult);
+      if (e == hipSuccess)
+        e = launch_bdf_wave(dm, env, d_state, n_cells, sp, d_status, d_stats, queue, grid, stream);
+      hipError_t e2 = hipFreeAsync(queue, stream);
+      if (e == hipSuccess) e = e2;
+    } else {
+      e = launch_bdf_wave(dm, env, d_state, n_cells, sp, d_status, d_stats, nullptr, n_cells, stream);
+    }
+  }
+  if (e != hipSuccess) return hip_fail(e, "solve launch");
+  return CAMP_OK;
+}
+
+Tuning default_tuning(const DevMech& dm, int n_cells) {
+  Tuning t;
+  const bool fits_wave = (dm.N + kWave - 1) / kWave <= 9 && wave_lds_bytes(dm) <= 160 * 1024;
+  t.engine = fits_wave ? CAMP_ENGINE_FUSED_WAVE : CAMP_ENGINE_FUSED_LANE;
+  t.persistent = 1;
+  const size_t lds = wave_lds_bytes(dm);
+  int per_cu = (int)std::max<size_t>(1, (160 * 1024) / std::max<size_t>(lds, 1));
+  t.grid_mult = std::min(per_cu, 32);
+  (void)n_cells;
+  return t;
+}
+
+int autotuned(camp_mech* mh, const DevMech& dm, int n_cells, Tuning* out);
+
+}  // namespace camp
+
+using namespace camp;
+
+extern "C" {
+
+const char* camp_last_error(void) { return g_err.c_str(); }
+
+int camp_mech_load(const camp_reaction* rxns, int n_rxn, const camp_species* species, int n_species,
+                   const camp_phase* phases, int n_phases, camp_mech** out) {
+  if (!out) { set_error("out is NULL"); return CAMP_EINVAL; }
+  *out = nullptr;
+  camp_mech* mh = new (std::nothrow) camp_mech();
+  if (!mh) { set_error("out of host memory"); return CAMP_ENOMEM; }
+  try {
+    std::string err = compile_mechanism(rxns, n_rxn, species, n_species, phases, n_phases, mh->C);
+    if (!err.empty()) {
+      delete mh;
+      set_error(err);
+      return CAMP_EINVAL;
+    }
+    mh->wlu = build_wave_schedule(mh->C.lu_tasks, mh->C.lu_level_ptr, kWave);
+    mh->wfwd = build_wave_schedule(mh->C.fwd_tasks, mh->C.fwd_level_ptr, kWave);
+    mh->wbwd = build_wave_schedule(mh->C.bwd_tasks, mh->C.bwd_level_ptr, kWave);
+  } catch (const std::bad_alloc&) {
+    delete mh;
+    set_error("out of host memory");
+    return CAMP_ENOMEM;
+  }
+  *out = mh;
+  return CAMP_OK;
+}
+
+int camp_mech_info(const camp_mech* mh, camp_mech_info_t* info) {
+  if (!mh || !info) { set_error("NULL argument"); return CAMP_EINVAL; }
+  const Compiled& C = mh->C;
+  info->n_state = C.n_state;
+  info->n_gas = C.n_gas;
+  info->n_instances = C.n_inst;
+  info->n_rxn_expanded = C.n_rxn;
+  info->n_external = C.n_ext;
+  info->nnz_pattern = C.nnz0;
+  info->nnz_fill = C.nnz;
+  info->lu_pairs = C.lu_pairs;
+  info->lu_levels = C.lu_levels();
+  info->fwd_levels = C.fwd_levels();
+  info->bwd_levels = C.bwd_levels();
+  info->n_partials = C.n_partials;
+  info->n_terms = (int)C.term_rxn.size();
+  info->n_jac_contrib = (int)C.jc_part.size();
+  return CAMP_OK;
+}
+
+int camp_mech_export(const camp_mech* mh, int* perm, int* row_ptr, int* col, int* pattern0) {
+  if (!mh) { set_error("NULL mechanism"); return CAMP_EINVAL; }
+  const Compiled& C = mh->C;
+  if (perm) std::copy(C.perm.begin(), C.perm.end(), perm);
+  if (row_ptr) std::copy(C.row_ptr.begin(), C.row_ptr.end(), row_ptr);
+  if (col) std::copy(C.col.begin(), C.col.end(), col);
+  if (pattern0)
+    for (int s = 0; s < C.nnz; ++s) pattern0[s] = C.pattern0[s];
+  return CAMP_OK;
+}
+
+void camp_mech_free(camp_mech* mh) {
+  if (!mh) return;
+  for (auto& kv : mh->dev) {
+    int cur = 0;
+    hipGetDevice(&cur);
+    hipSetDevice(kv.first);
+    hipDeviceSynchronize();
+    hipFree(kv.second.blob);
+    hipSetDevice(cur);
+  }
+  delete mh;
+}
+
+int camp_solve_device(camp_mech* mh, int n_cells, double* d_state, const camp_env* d_env, double dt,
+                      double rtol, double atol, const camp_opts* opts, int* d_status,
+                      camp_cell_stats* d_stats, void* stream) {
+  int rc = check_solve_args(mh, n_cells, d_state, d_env, dt, rtol, atol);
+  if (rc != CAMP_OK) return rc;
+  if (n_cells > 0 && !d_status) { set_error("d_cell_status is required"); return CAMP_EINVAL; }
+  if (n_cells == 0) return CAMP_OK;
+  const DevMech* dm = nullptr;
+  rc = resident(mh, &dm);
+  if (rc != CAMP_OK) return rc;
+  const SolveParams sp = make_params(dt, rtol, atol, opts);
+  Tuning tu;
+  const int engine = opts ? opts->engine : CAMP_ENGINE_AUTO;
+  if (engine == CAMP_ENGINE_AUTO) {
+    rc = autotuned(mh, *dm, n_cells, &tu);
+    if (rc != CAMP_OK) return rc;
+  } else {
+    tu = default_tuning(*dm, n_cells);
+    tu.engine = engine;
+  }
+  if (opts && opts->persistent >= 0 && engine != CAMP_ENGINE_AUTO) tu.persistent = opts->persistent ? 1 : 0;
+  if (opts && opts->wg_per_cu > 0 && engine != CAMP_ENGINE_AUTO) tu.grid_mult = opts->wg_per_cu;
+  return solve_device_tuned(mh, *dm, n_cells, d_state, d_env, sp, opts, d_status, d_stats,
+                            (hipStream_t)stream, tu);
+}
+
+int camp_solve(camp_mech* mh, int n_cells, double* state, const camp_env* env, double dt, double rtol,
+               double atol, const camp_opts* opts, int* cell_status, camp_cell_stats* cell_stats) {
+  int rc = check_solve_args(mh, n_cells, state, env, dt, rtol, atol);
+  if (rc != CAMP_OK) return rc;
+  if (n_cells == 0) return CAMP_OK;
+  const Compiled& C = mh->C;
+  const size_t n = (size_t)n_cells;
+  const size_t bytes_state = 8 * n * C.n_state;
+  const size_t bytes_inst = 8 * n * C.n_inst;
+  const size_t bytes_ovr = 8 * n * C.n_ext;
+  struct Part {
+    const void* src;
+    size_t bytes;
+    size_t off;
+  } parts[7];
+  size_t total = 0;
+  auto add = [&](int i, const void* src, size_t bytes) {
+    parts[i] = {src, src ? bytes : 0, total};
+    total = align256(total + (src ? bytes : 0));
+  };
+  add(0, state, bytes_state);
+  add(1, env->T_K, 8 * n);
+  add(2, env->P_Pa, 8 * n);
+  add(3, env->cos_sza, 8 * n);
+  add(4, C.n_inst ? env->radius_m : nullptr, bytes_inst);
+  add(5, C.n_inst ? env->aer_mass_kg_m3 : nullptr, bytes_inst);
+  add(6, env->rate_override, bytes_ovr);
+  const size_t off_status = total;
+  total = align256(total + 4 * n);
+  const size_t off_stats = total;
+  if (cell_stats) total = align256(total + sizeof(camp_cell_stats) * n);
+  char* d = nullptr;
+  hipError_t e = hipMalloc((void**)&d, total);
+  if (e != hipSuccess) return hip_fail(e, "hipMalloc(solve buffers)");
+  for (auto& p : parts)
+    if (p.bytes) {
+      e = hipMemcpy(d + p.off, p.src, p.bytes, hipMemcpyHostToDevice);
+      if (e != hipSuccess) { hipFree(d); return hip_fail(e, "hipMemcpy H2D"); }
+    }
+  camp_env denv{(const double*)(d + parts[1].off), (const double*)(d + parts[2].off),
+                parts[3].bytes ? (const double*)(d + parts[3].off) : nullptr,
+                parts[4].bytes ? (const double*)(d + parts[4].off) : nullptr,
+                parts[5].bytes ? (const double*)(d + parts[5].off) : nullptr,
+                parts[6].bytes ? (const double*)(d + parts[6].off) : nullptr};
+  int* d_status = (int*)(d + off_status);
+  camp_cell_stats* d_stats = cell_stats ? (camp_cell_stats*)(d + off_stats) : nullptr;
+  rc = camp_solve_device(mh, n_cells, (double*)(d + parts[0].off), &denv, dt, rtol, atol, opts,
+                         d_status, d_stats, nullptr);
+  if (rc == CAMP_OK) {
+    e = hipDeviceSynchronize();
+    if (e != hipSuccess) rc = hip_fail(e, "solve");
+  }
+  std::vector<int> st(n);
+  if (rc == CAMP_OK) {
+    e = hipMemcpy(state, d + parts[0].off, bytes_state, hipMemcpyDeviceToHost);
+    if (e == hipSuccess) e = hipMemcpy(st.data(), d_status, 4 * n, hipMemcpyDeviceToHost);
+    if (e == hipSuccess && cell_stats)
+      e = hipMemcpy(cell_stats, d_stats, sizeof(camp_cell_stats) * n, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) rc = hip_fail(e, "hipMemcpy D2H");
+  }
+  hipFree(d);
+  if (rc != CAMP_OK) return rc;
+  if (cell_status) std::copy(st.begin(), st.end(), cell_status);
+  for (int s : st)
+    if (s != 0) {
+      set_error("one or more cells failed; see cell_status");
+      return CAMP_ESOLVE;
+    }
+  return CAMP_OK;
+}
+
+int camp_rate_constants_device(camp_mech* mh, int n_cells, const camp_env* d_env, double* d_k,
+                               void* stream) {
+  if (!mh || !d_env || n_cells < 0 || (n_cells > 0 && (!d_k || !d_env->T_K || !d_env->P_Pa))) {
+    set_error("bad argument");
+    return CAMP_EINVAL;
+  }
+  if (n_cells == 0) return CAMP_OK;
+  const DevMech* dm = nullptr;
+  int rc = resident(mh, &dm);
+  if (rc != CAMP_OK) return rc;
+  hipError_t e = launch_rates_step(*dm, make_env(d_env), n_cells, d_k, (hipStream_t)stream);
+  return e == hipSuccess ? CAMP_OK : hip_fail(e, "rate constants");
+}
+
+static int step_common(camp_mech* mh, int n_cells, int op, const double* kin, const double* yin,
+                       double* out, double gamma, void* stream) {
+  if (!mh || n_cells < 0 || (n_cells > 0 && !out)) { set_error("bad argument"); return CAMP_EINVAL; }
+  if (n_cells == 0) return CAMP_OK;
+  const DevMech* dm = nullptr;
+  int rc = resident(mh, &dm);
+  if (rc != CAMP_OK) return rc;
+  hipError_t e = launch_wave_step(*dm, op, n_cells, kin, yin, out, gamma, (hipStream_t)stream);
+  return e == hipSuccess ? CAMP_OK : hip_fail(e, "step kernel");
+}
+
+int camp_forcing_device(camp_mech* mh, int n_cells, const double* d_k, const double* d_y, double* d_f,
+                        void* stream) {
+  if (n_cells > 0 && (!d_k || !d_y)) { set_error("bad argument"); return CAMP_EINVAL; }
+  return step_common(mh, n_cells, 0, d_k, d_y, d_f, 0.0, stream);
+}
+
+int camp_newton_matrix_device(camp_mech* mh, int n_cells, const double* d_k, const double* d_y,
+                              double gamma, double* d_m, void* stream) {
+  if (n_cells > 0 && (!d_k || !d_y)) { set_error("bad argument"); return CAMP_EINVAL; }
+  return step_common(mh, n_cells, 1, d_k, d_y, d_m, gamma, stream);
+}
+
+int camp_lu_factor_device(camp_mech* mh, int n_cells, double* d_m, void* stream) {
+  return step_common(mh, n_cells, 2, nullptr, nullptr, d_m, 0.0, stream);
+}
+
+int camp_lu_solve_device(camp_mech* mh, int n_cells, const double* d_lu, double* d_b, void* stream) {
+  if (n_cells > 0 && !d_lu) { set_error("bad argument"); return CAMP_EINVAL; }
+  return step_common(mh, n_cells, 3, d_lu, nullptr, d_b, 0.0, stream);
+}
+
+int camp_count_failed(int n_cells, const int* d_status, int* n_failed, void* stream) {
+  if (n_cells < 0 || !n_failed || (n_cells > 0 && !d_status)) { set_error("bad argument"); return CAMP_EINVAL; }
+  *n_failed = 0;
+  if (n_cells == 0) return CAMP_OK;
+  int* d = nullptr;
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e = hipMallocAsync((void**)&d, 256, s);
+  if (e != hipSuccess) return hip_fail(e, "hipMallocAsync");
+  e = launch_count_failed(n_cells, d_status, d, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(n_failed, d, sizeof(int), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  hipFreeAsync(d, s);
+  return e == hipSuccess ? CAMP_OK : hip_fail(e, "count failed");
+}
+
+}  // extern "C"

@@ -1,0 +1,79 @@
+// Scalar BDF control shared by the engines: constants, starting step, step/order choice.
+//
+// The integrator is variable-order (1..5), variable-step BDF in backward-difference form
+// (Shampine & Reichelt 1997, kappa = 0) with a modified Newton iteration: the Newton
+// matrix I - c J (c = h / gamma_q) is factored once and reused until c drifts by more than
+// 30 % or 20 steps pass, and a correction computed with a stale c is scaled by
+// 2 / (1 + c / c_lu) (Brown, Byrne & Hindmarsh 1989). Convergence uses the estimated
+// contraction rate (Newton tolerance 0.1 of the local error tolerance, CVODE's published
+// default). The paper specifies only that CVODE's variable-order, variable-step BDF with
+// Newton iteration and error control is used (Sect. 2.4.1).
+#pragma once
+
+#include "device.hpp"
+
+namespace camp {
+
+constexpr double kSafety = 0.9;
+constexpr double kMinFactor = 0.2;
+constexpr double kMaxFactor = 5.0;
+constexpr double kLuGammaDrift = 0.3;
+constexpr int kLuMaxAge = 20;
+constexpr int kMaxConsecFail = 10;
+constexpr double kNewtonDiverge = 2.0;
+// Repeated local-error failures at one step (CVODE's published recovery): from the second
+// failure the step factor is at most kMinFactor; from the third the method restarts at
+// order 1 from y_n with the step cut by kRestartFactor.
+constexpr int kErrRestart = 3;
+constexpr double kRestartFactor = 0.1;
+
+enum CellStatus : int { ST_OK = 0, ST_MAX_STEPS = 1, ST_H_MIN = 2, ST_ERR_FAIL = 3,
+                        ST_NEWTON_FAIL = 4, ST_NONFINITE = 5 };
+
+// Matrix T = (R(rho) R(1))^T restricted to 0..q, R_{k,m}(rho) = prod_{i=1}^{k}(i-1-m rho)/i:
+// D_new[j] = sum_k T[j][k] D_old[k]. Row/col 0 is the identity.
+__device__ inline void rescale_matrix(int q, double rho, double T[kMaxOrder + 1][kMaxOrder + 1]) {
+  double Rr[kMaxOrder + 1][kMaxOrder + 1], Ru[kMaxOrder + 1][kMaxOrder + 1];
+  for (int m = 0; m <= q; ++m) {
+    Rr[0][m] = 1.0;
+    Ru[0][m] = 1.0;
+  }
+  for (int k = 1; k <= q; ++k)
+    for (int m = 0; m <= q; ++m) {
+      Rr[k][m] = Rr[k - 1][m] * ((k - 1) - m * rho) / k;
+      Ru[k][m] = Ru[k - 1][m] * (double)((k - 1) - m) / k;
+    }
+  // (Rr Ru)^T [j][k] = sum_m Rr[k][m] Ru[m][j]
+  for (int j = 0; j <= q; ++j)
+    for (int k = 0; k <= q; ++k) {
+      double s = 0.0;
+      for (int m = 0; m <= q; ++m) s += Rr[k][m] * Ru[m][j];
+      T[j][k] = s;
+    }
+}
+
+// Starting step (Hairer, Norsett & Wanner I, Sect. II.4) for order 1.
+__device__ inline double starting_step_h0(double d0, double d1, double span) {
+  double h0 = (d0 < 1e-5 || d1 < 1e-5) ? 1e-6 : 0.01 * d0 / d1;
+  return fmin(h0, span);
+}
+__device__ inline double starting_step(double h0, double d1, double d2, double span) {
+  double h1 = (d1 <= 1e-15 && d2 <= 1e-15) ? fmax(1e-6, h0 * 1e-3) : sqrt(0.01 / fmax(d1, d2));
+  return fmin(fmin(100.0 * h0, h1), span);
+}
+
+// Order/step choice after q+1 equal steps: returns the new order, writes the factor.
+__device__ inline int choose_order(int q, int max_order, double err, double err_m, double err_p,
+                                   double* factor) {
+  double fm = (q > 1 && err_m > 0.0) ? pow(err_m, -1.0 / q) : (q > 1 ? 1e30 : 0.0);
+  double f0 = err > 0.0 ? pow(err, -1.0 / (q + 1)) : 1e30;
+  double fp = (q < max_order && err_p > 0.0) ? pow(err_p, -1.0 / (q + 2)) : (q < max_order ? 1e30 : 0.0);
+  double best = f0;
+  int dq = 0;
+  if (fm > best) { best = fm; dq = -1; }
+  if (fp > best) { best = fp; dq = +1; }
+  *factor = fmin(kMaxFactor, kSafety * best);
+  return q + dq;
+}
+
+}  // namespace camp

@@ -1,0 +1,630 @@
+// Host mechanism compiler: validation, phase x instance expansion, state ids, Jacobian
+// pattern, fill-reducing order, symbolic LU fill and level-scheduled tables.
+//
+// The paper's Processes declare at initialization the Jacobian elements they contribute to
+// (so the solver may use a sparse Jacobian) and receive ids for species and Jacobian
+// elements for use during solving (table of Process functions: get_used_jacobian_elements,
+// update_ids). Processes on an aerosol phase apply to every instance of the phase
+// (Sect. 2.2.3). The linear solver is a sparse direct LU (Sect. 2.4.1, KLU); here its
+// pattern, fill and elimination schedule are fixed once per mechanism so every cell of
+// every call shares them.
+#include <algorithm>
+#include <cmath>
+#include <numeric>
+#include <set>
+#include <sstream>
+
+#include "mech.hpp"
+
+namespace camp {
+
+namespace {
+
+constexpr double kAvogadro = 6.02214076e23;
+
+bool finite(double v) { return std::isfinite(v); }
+
+struct Bits {
+  int n = 0, words = 0;
+  std::vector<uint64_t> w;
+  void init(int n_, int rows) {
+    n = n_;
+    words = (n + 63) / 64;
+    w.assign((size_t)words * rows, 0);
+  }
+  uint64_t* row(int r) { return w.data() + (size_t)r * words; }
+  bool get(int r, int c) const { return (w[(size_t)r * words + c / 64] >> (c % 64)) & 1u; }
+  void set(int r, int c) { w[(size_t)r * words + c / 64] |= (uint64_t)1 << (c % 64); }
+};
+
+// Exact minimum degree on the symmetrized pattern (elimination-graph model); ties go to
+// the lowest index, so the order is deterministic.
+std::vector<int> minimum_degree(int n, const std::vector<std::pair<int, int>>& edges) {
+  std::vector<std::set<int>> adj(n);
+  for (auto& e : edges)
+    if (e.first != e.second) {
+      adj[e.first].insert(e.second);
+      adj[e.second].insert(e.first);
+    }
+  std::vector<char> alive(n, 1);
+  std::vector<int> order;
+  order.reserve(n);
+  for (int step = 0; step < n; ++step) {
+    int best = -1;
+    size_t bd = 0;
+    for (int v = 0; v < n; ++v)
+      if (alive[v] && (best < 0 || adj[v].size() < bd)) {
+        best = v;
+        bd = adj[v].size();
+      }
+    order.push_back(best);
+    alive[best] = 0;
+    std::vector<int> nb(adj[best].begin(), adj[best].end());
+    for (int a : nb) {
+      adj[a].erase(best);
+      for (int b : nb)
+        if (b != a) adj[a].insert(b);
+    }
+    adj[best].clear();
+  }
+  return order;
+}
+
+}  // namespace
+
+std::string compile_mechanism(const camp_reaction* rxns, int n_rxn, const camp_species* sp,
+                              int n_sp, const camp_phase* ph, int n_ph, Compiled& C) {
+  std::ostringstream err;
+  if (n_sp <= 0 || !sp) return "mechanism has no species";
+  if (n_rxn < 0 || (n_rxn > 0 && !rxns)) return "bad reaction array";
+  if (n_ph < 0 || (n_ph > 0 && !ph)) return "bad phase array";
+
+  // ---- species and phases ----
+  std::vector<int> gas_state(n_sp, -1), sp_phase(n_sp), pos_in_phase(n_sp, -1);
+  int n_gas = 0;
+  for (int s = 0; s < n_sp; ++s) {
+    sp_phase[s] = sp[s].phase;
+    if (sp[s].phase < -1 || sp[s].phase >= n_ph) {
+      err << "species " << s << " has invalid phase " << sp[s].phase;
+      return err.str();
+    }
+    if (sp[s].phase < 0) gas_state[s] = n_gas++;
+  }
+  std::vector<int> phase_first_inst(n_ph), phase_base(n_ph);
+  int n_inst = 0, pos = n_gas;
+  for (int p = 0; p < n_ph; ++p) {
+    const camp_phase& q = ph[p];
+    if (q.n_species < 1 || !q.species) {
+      err << "phase " << p << " has no species";
+      return err.str();
+    }
+    if (q.n_instances < 1) {
+      err << "phase " << p << " has no instances";
+      return err.str();
+    }
+    if (!(q.density_kg_m3 > 0) || !finite(q.density_kg_m3) || !(q.mw_absorber_kg_mol > 0) ||
+        !finite(q.mw_absorber_kg_mol)) {
+      err << "phase " << p << " needs positive finite density and absorber molar mass";
+      return err.str();
+    }
+    for (int k = 0; k < q.n_species; ++k) {
+      int s = q.species[k];
+      if (s < 0 || s >= n_sp || sp[s].phase != p || pos_in_phase[s] >= 0) {
+        err << "phase " << p << " lists species " << s << " that does not belong to it";
+        return err.str();
+      }
+      pos_in_phase[s] = k;
+    }
+    phase_first_inst[p] = n_inst;
+    phase_base[p] = pos;
+    for (int i = 0; i < q.n_instances; ++i) {
+      C.inst_phase.push_back(p);
+      C.inst_base.push_back(pos);
+      pos += q.n_species;
+    }
+    n_inst += q.n_instances;
+  }
+  for (int s = 0; s < n_sp; ++s)
+    if (sp[s].phase >= 0 && pos_in_phase[s] < 0) {
+      err << "species " << s << " is not listed by its phase";
+      return err.str();
+    }
+  const int N = pos;
+  C.n_state = N;
+  C.n_gas = n_gas;
+  C.n_inst = n_inst;
+
+  auto cond_state = [&](int p, int inst_local, int s) {
+    return phase_base[p] + inst_local * ph[p].n_species + pos_in_phase[s];
+  };
+
+  // ---- expansion ----
+  struct X {
+    int nr, np;
+    int react[3], prod[3];
+    double yld[3];
+  };
+  std::vector<X> xs;
+  std::vector<RateSpec> rs;
+  int n_ext = 0;
+  for (int r = 0; r < n_rxn; ++r) {
+    const camp_reaction& q = rxns[r];
+    for (int v = 0; v < 6; ++v)
+      if (!finite(q.p[v])) {
+        err << "reaction " << r << " has a non-finite parameter";
+        return err.str();
+      }
+    if (q.n_react < 0 || q.n_react > 3 || q.n_prod < 0 || q.n_prod > 3) {
+      err << "reaction " << r << ": n_react and n_prod must be within 0..3";
+      return err.str();
+    }
+    for (int k = 0; k < q.n_react; ++k)
+      if (q.react[k] < 0 || q.react[k] >= n_sp) {
+        err << "reaction " << r << ": reactant id out of range";
+        return err.str();
+      }
+    for (int k = 0; k < q.n_prod; ++k) {
+      if (q.prod[k] < 0 || q.prod[k] >= n_sp) {
+        err << "reaction " << r << ": product id out of range";
+        return err.str();
+      }
+      if (!finite(q.yield[k]) || q.yield[k] < 0) {
+        err << "reaction " << r << ": yields must be finite and >= 0";
+        return err.str();
+      }
+      for (int k2 = 0; k2 < k; ++k2)
+        if (q.prod[k2] == q.prod[k]) {
+          err << "reaction " << r << ": duplicate product";
+          return err.str();
+        }
+    }
+    const int t = q.type;
+    auto base_spec = [&](int kind) {
+      RateSpec s{};
+      s.kind = kind;
+      s.ext = -1;
+      s.inst = -1;
+      return s;
+    };
+    if (t == CAMP_RXN_ARRHENIUS || t == CAMP_RXN_PHOTOLYSIS || t == CAMP_RXN_EMISSION ||
+        t == CAMP_RXN_FIRST_ORDER_LOSS) {
+      for (int k = 0; k < q.n_react; ++k)
+        if (gas_state[q.react[k]] < 0) {
+          err << "reaction " << r << ": gas-phase process with a condensed reactant";
+          return err.str();
+        }
+      for (int k = 0; k < q.n_prod; ++k)
+        if (gas_state[q.prod[k]] < 0) {
+          err << "reaction " << r << ": gas-phase process with a condensed product";
+          return err.str();
+        }
+      RateSpec s;
+      if (t == CAMP_RXN_ARRHENIUS) {
+        if (q.p[0] < 0 || (q.p[2] != 0.0 && !(q.p[3] > 0))) {
+          err << "reaction " << r << ": Arrhenius needs A >= 0 and D > 0 when B != 0";
+          return err.str();
+        }
+        s = base_spec(KR_ARRHENIUS);
+        s.v[0] = q.p[0] * std::pow(kAvogadro * 1.0e-6, q.n_react - 1);
+        s.v[1] = q.p[1];
+        s.v[2] = q.p[2];
+        s.v[3] = q.p[3];
+        s.v[4] = q.p[4];
+      } else {
+        if (q.p[0] < 0) {
+          err << "reaction " << r << ": negative rate";
+          return err.str();
+        }
+        if (t == CAMP_RXN_PHOTOLYSIS && q.n_react != 1) {
+          err << "reaction " << r << ": photolysis needs exactly one reactant";
+          return err.str();
+        }
+        if (t == CAMP_RXN_EMISSION && (q.n_react != 0 || q.n_prod != 1)) {
+          err << "reaction " << r << ": emission needs 0 reactants and 1 product";
+          return err.str();
+        }
+        if (t == CAMP_RXN_FIRST_ORDER_LOSS && (q.n_react != 1 || q.n_prod != 0)) {
+          err << "reaction " << r << ": first-order loss needs 1 reactant and 0 products";
+          return err.str();
+        }
+        s = base_spec(t == CAMP_RXN_PHOTOLYSIS ? KR_PHOTOLYSIS
+                                                : t == CAMP_RXN_EMISSION ? KR_EMISSION : KR_LOSS);
+        s.v[0] = q.p[0];
+        s.v[1] = q.p[1];
+        s.ext = n_ext++;
+      }
+      X x{};
+      x.nr = q.n_react;
+      x.np = q.n_prod;
+      for (int k = 0; k < q.n_react; ++k) x.react[k] = gas_state[q.react[k]];
+      for (int k = 0; k < q.n_prod; ++k) {
+        x.prod[k] = gas_state[q.prod[k]];
+        x.yld[k] = q.yield[k];
+      }
+      s.nr = x.nr;
+      xs.push_back(x);
+      rs.push_back(s);
+    } else if (t == CAMP_RXN_CONDENSED_ARRHENIUS) {
+      const int p = q.phase;
+      if (p < 0 || p >= n_ph) {
+        err << "reaction " << r << ": condensed-phase process needs a valid phase";
+        return err.str();
+      }
+      for (int k = 0; k < q.n_react; ++k)
+        if (sp_phase[q.react[k]] != p) {
+          err << "reaction " << r << ": reactant not in the reaction's phase";
+          return err.str();
+        }
+      for (int k = 0; k < q.n_prod; ++k)
+        if (sp_phase[q.prod[k]] != p) {
+          err << "reaction " << r << ": product not in the reaction's phase";
+          return err.str();
+        }
+      if (q.p[0] < 0 || (q.p[2] != 0.0 && !(q.p[3] > 0))) {
+        err << "reaction " << r << ": Arrhenius needs A >= 0 and D > 0 when B != 0";
+        return err.str();
+      }
+      for (int i = 0; i < ph[p].n_instances; ++i) {
+        RateSpec s = base_spec(KR_CONDENSED);
+        s.inst = phase_first_inst[p] + i;
+        for (int v = 0; v < 6; ++v) s.v[v] = q.p[v];
+        s.v[6] = ph[p].density_kg_m3;
+        s.nr = q.n_react;
+        X x{};
+        x.nr = q.n_react;
+        x.np = q.n_prod;
+        for (int k = 0; k < q.n_react; ++k) x.react[k] = cond_state(p, i, q.react[k]);
+        for (int k = 0; k < q.n_prod; ++k) {
+          x.prod[k] = cond_state(p, i, q.prod[k]);
+          x.yld[k] = q.yield[k];
+        }
+        xs.push_back(x);
+        rs.push_back(s);
+      }
+    } else if (t == CAMP_RXN_HENRY_TRANSFER || t == CAMP_RXN_SIMPOL_TRANSFER) {
+      const int p = q.phase;
+      if (p < 0 || p >= n_ph) {
+        err << "reaction " << r << ": transfer process needs a valid phase";
+        return err.str();
+      }
+      if (q.n_react != 1 || q.n_prod != 1 || gas_state[q.react[0]] < 0 ||
+          sp_phase[q.prod[0]] != p) {
+        err << "reaction " << r << ": transfer needs one gas-phase reactant and one product "
+                                   "in the reaction's phase";
+        return err.str();
+      }
+      const camp_species& g = sp[q.react[0]];
+      if (!(g.mw_kg_mol > 0) || !(g.diff_m2_s > 0) || !(g.accom > 0) || !finite(g.mw_kg_mol) ||
+          !finite(g.diff_m2_s) || !finite(g.accom)) {
+        err << "reaction " << r << ": gas partner needs positive MW, diffusion and accommodation";
+        return err.str();
+      }
+      if (t == CAMP_RXN_HENRY_TRANSFER && !(q.p[0] > 0)) {
+        err << "reaction " << r << ": Henry constant must be positive";
+        return err.str();
+      }
+      const bool henry = t == CAMP_RXN_HENRY_TRANSFER;
+      for (int i = 0; i < ph[p].n_instances; ++i) {
+        for (int dir = 0; dir < 2; ++dir) {
+          RateSpec s = base_spec(henry ? (dir == 0 ? KR_HENRY_COND : KR_HENRY_EVAP)
+                                       : (dir == 0 ? KR_SIMPOL_COND : KR_SIMPOL_EVAP));
+          s.inst = phase_first_inst[p] + i;
+          s.v[0] = g.diff_m2_s;
+          s.v[1] = g.mw_kg_mol;
+          s.v[2] = g.accom;
+          s.v[3] = ph[p].density_kg_m3;
+          s.v[4] = ph[p].mw_absorber_kg_mol;
+          for (int v = 0; v < 4; ++v) s.v[5 + v] = q.p[v];
+          s.nr = 1;
+          X x{};
+          x.nr = 1;
+          x.np = 1;
+          int gs = gas_state[q.react[0]], as = cond_state(p, i, q.prod[0]);
+          x.react[0] = dir == 0 ? gs : as;
+          x.prod[0] = dir == 0 ? as : gs;
+          x.yld[0] = 1.0;
+          xs.push_back(x);
+          rs.push_back(s);
+        }
+      }
+    } else {
+      err << "reaction " << r << ": unknown type " << t;
+      return err.str();
+    }
+  }
+  const int R = (int)xs.size();
+  C.n_rxn = R;
+  C.n_ext = n_ext;
+
+  // ---- net stoichiometry and the Jacobian pattern (user order) ----
+  // S[i][k] kept sparse: per reaction the distinct members with their net coefficient.
+  std::vector<std::vector<std::pair<int, double>>> members(R);
+  std::vector<std::pair<int, int>> edges;
+  for (int k = 0; k < R; ++k) {
+    const X& x = xs[k];
+    std::vector<std::pair<int, double>> m;
+    auto add = [&](int i, double c) {
+      for (auto& e : m)
+        if (e.first == i) {
+          e.second += c;
+          return;
+        }
+      m.push_back({i, c});
+    };
+    for (int o = 0; o < x.nr; ++o) add(x.react[o], -1.0);
+    for (int o = 0; o < x.np; ++o) add(x.prod[o], x.yld[o]);
+    members[k] = m;
+    for (int o = 0; o < x.nr; ++o)
+      for (auto& e : m) edges.push_back({e.first, x.react[o]});   // (row i, col j)
+  }
+  for (int i = 0; i < N; ++i) edges.push_back({i, i});
+
+  // ---- elimination order and symbolic fill ----
+  C.perm = minimum_degree(N, edges);
+  C.iperm.assign(N, 0);
+  for (int t = 0; t < N; ++t) C.iperm[C.perm[t]] = t;
+
+  Bits F, F0;
+  F.init(N, N);
+  F0.init(N, N);
+  for (auto& e : edges) {
+    F.set(C.iperm[e.first], C.iperm[e.second]);
+    F0.set(C.iperm[e.first], C.iperm[e.second]);
+  }
+  for (int k = 0; k < N; ++k) {
+    // rows i > k with (i, k): OR row k's entries right of k into row i
+    for (int i = k + 1; i < N; ++i) {
+      if (!F.get(i, k)) continue;
+      uint64_t* ri = F.row(i);
+      const uint64_t* rk = F.row(k);
+      for (int w = 0; w < F.words; ++w) {
+        uint64_t m = rk[w];
+        int lo = w * 64;
+        if (lo + 63 <= k) continue;
+        if (lo <= k) m &= ~((k - lo == 63) ? ~0ull : ((1ull << (k - lo + 1)) - 1));
+        ri[w] |= m;
+      }
+    }
+  }
+
+  // ---- CSR of the filled pattern ----
+  C.row_ptr.assign(N + 1, 0);
+  C.diag.assign(N, -1);
+  for (int i = 0; i < N; ++i) {
+    for (int j = 0; j < N; ++j)
+      if (F.get(i, j)) {
+        if (i == j) C.diag[i] = (int)C.col.size();
+        C.col.push_back(j);
+        C.pattern0.push_back(F0.get(i, j) ? 1 : 0);
+      }
+    C.row_ptr[i + 1] = (int)C.col.size();
+  }
+  C.nnz = (int)C.col.size();
+  C.nnz0 = 0;
+  for (char c : C.pattern0) C.nnz0 += c;
+  auto slot = [&](int i, int j) -> int {
+    auto b = C.col.begin() + C.row_ptr[i], e = C.col.begin() + C.row_ptr[i + 1];
+    auto it = std::lower_bound(b, e, j);
+    return (it != e && *it == j) ? (int)(it - C.col.begin()) : -1;
+  };
+
+  // ---- device reaction tables (elimination positions) ----
+  C.rate = rs;
+  C.rx_react.assign((size_t)R * 3, -1);
+  C.rx_nr.assign(R, 0);
+  C.rx_pofs.assign(R + 1, 0);
+  for (int k = 0; k < R; ++k) {
+    C.rx_nr[k] = xs[k].nr;
+    for (int o = 0; o < xs[k].nr; ++o) C.rx_react[3 * k + o] = C.iperm[xs[k].react[o]];
+    C.rx_pofs[k + 1] = C.rx_pofs[k] + xs[k].nr;
+  }
+  C.n_partials = C.rx_pofs[R];
+
+  // forcing terms by species (elimination position), reactions ascending
+  {
+    std::vector<std::vector<std::pair<int, double>>> by(N);
+    for (int k = 0; k < R; ++k)
+      for (auto& e : members[k])
+        if (e.second != 0.0) by[C.iperm[e.first]].push_back({k, e.second});
+    C.term_ptr.assign(N + 1, 0);
+    for (int t = 0; t < N; ++t) {
+      for (auto& e : by[t]) {
+        C.term_rxn.push_back(e.first);
+        C.term_coef.push_back(e.second);
+      }
+      C.term_ptr[t + 1] = (int)C.term_rxn.size();
+    }
+  }
+  // Jacobian contributions by slot: J[i][j] += S[i][k] * partial(k, o) for react[k][o] == j
+  {
+    std::vector<std::vector<std::pair<int, double>>> by(C.nnz);
+    for (int k = 0; k < R; ++k)
+      for (int o = 0; o < xs[k].nr; ++o) {
+        int j = C.iperm[xs[k].react[o]];
+        for (auto& e : members[k]) {
+          if (e.second == 0.0) continue;
+          int s = slot(C.iperm[e.first], j);
+          by[s].push_back({C.rx_pofs[k] + o, e.second});
+        }
+      }
+    C.jc_ptr.assign(C.nnz + 1, 0);
+    for (int s = 0; s < C.nnz; ++s) {
+      for (auto& e : by[s]) {
+        C.jc_part.push_back(e.first);
+        C.jc_coef.push_back(e.second);
+      }
+      C.jc_ptr[s + 1] = (int)C.jc_part.size();
+    }
+  }
+
+  // ---- Crout LU tasks: one per computed entry, in dependency levels ----
+  // U entry (i <= j): u_ij = m_ij - sum_{k < i} l_ik u_kj
+  // L entry (i >  j): l_ij = (m_ij - sum_{k < j} l_ik u_kj) / u_jj
+  {
+    std::vector<int> level(C.nnz, 0);
+    struct Pending {
+      Task t;
+      int level;
+      std::vector<std::pair<int, int>> pairs;
+    };
+    std::vector<Pending> pend;
+    auto make = [&](int i, int j) {
+      int s = slot(i, j);
+      int m = std::min(i, j);
+      Pending p;
+      p.t.dst = s;
+      p.t.diag = (i > j) ? C.diag[j] : -1;
+      int lv = 0;
+      for (int q = C.row_ptr[i]; q < C.row_ptr[i + 1] && C.col[q] < m; ++q) {
+        int k = C.col[q];
+        int skj = slot(k, j);
+        if (skj < 0) continue;
+        p.pairs.push_back({q, skj});
+        lv = std::max(lv, std::max(level[q], level[skj]));
+      }
+      if (p.t.diag >= 0) lv = std::max(lv, level[p.t.diag]);
+      if (p.pairs.empty() && p.t.diag < 0) return;   // value is final as given
+      level[s] = lv + 1;
+      p.level = lv + 1;
+      pend.push_back(std::move(p));
+    };
+    for (int m = 0; m < N; ++m) {
+      for (int q = C.row_ptr[m]; q < C.row_ptr[m + 1]; ++q)
+        if (C.col[q] >= m) make(m, C.col[q]);
+      for (int i = m + 1; i < N; ++i)
+        if (slot(i, m) >= 0) make(i, m);
+    }
+    int L = 0;
+    for (auto& p : pend) L = std::max(L, p.level);
+    std::stable_sort(pend.begin(), pend.end(),
+                     [](const Pending& a, const Pending& b) { return a.level < b.level; });
+    C.lu_level_ptr.assign(L + 1, 0);
+    for (auto& p : pend) {
+      Task t = p.t;
+      t.pbeg = (int)C.lu_pa.size();
+      for (auto& pr : p.pairs) {
+        C.lu_pa.push_back(pr.first);
+        C.lu_pb.push_back(pr.second);
+      }
+      t.pend = (int)C.lu_pa.size();
+      C.lu_tasks.push_back(t);
+      C.lu_level_ptr[p.level]++;   // count, prefix-summed below (levels start at 1)
+    }
+    // level_ptr[l] .. level_ptr[l+1] for l = 0..L-1 holds level l+1
+    std::vector<int> cnt(C.lu_level_ptr);
+    C.lu_level_ptr.assign(L + 1, 0);
+    for (int l = 1; l <= L; ++l) C.lu_level_ptr[l] = C.lu_level_ptr[l - 1] + cnt[l];
+    C.lu_pairs = (long long)C.lu_pa.size();
+  }
+
+  // ---- triangular solves ----
+  {
+    // forward, unit lower: x_t -= sum_{k < t} l_tk x_k
+    std::vector<int> lv(N, 0);
+    std::vector<std::pair<int, Task>> tk;
+    std::vector<std::vector<std::pair<int, int>>> prs;
+    for (int t = 0; t < N; ++t) {
+      Task T{t, -1, 0, 0};
+      std::vector<std::pair<int, int>> pp;
+      int l = 0;
+      for (int q = C.row_ptr[t]; q < C.row_ptr[t + 1] && C.col[q] < t; ++q) {
+        pp.push_back({q, C.col[q]});
+        l = std::max(l, lv[C.col[q]]);
+      }
+      if (pp.empty()) continue;
+      lv[t] = l + 1;
+      tk.push_back({l + 1, T});
+      prs.push_back(pp);
+    }
+    std::vector<int> idx(tk.size());
+    std::iota(idx.begin(), idx.end(), 0);
+    std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) { return tk[a].first < tk[b].first; });
+    int L = tk.empty() ? 0 : tk[idx.back()].first;
+    C.fwd_level_ptr.assign(L + 1, 0);
+    for (int a : idx) {
+      Task T = tk[a].second;
+      T.pbeg = (int)C.fwd_pa.size();
+      for (auto& pr : prs[a]) {
+        C.fwd_pa.push_back(pr.first);
+        C.fwd_pb.push_back(pr.second);
+      }
+      T.pend = (int)C.fwd_pa.size();
+      C.fwd_tasks.push_back(T);
+      C.fwd_level_ptr[tk[a].first]++;
+    }
+    for (int l = 1; l <= L; ++l) C.fwd_level_ptr[l] += C.fwd_level_ptr[l - 1];
+  }
+  {
+    // backward: x_t = (x_t - sum_{j > t} u_tj x_j) / u_tt
+    std::vector<int> lv(N, 0);
+    std::vector<std::pair<int, Task>> tk;
+    std::vector<std::vector<std::pair<int, int>>> prs;
+    for (int t = N - 1; t >= 0; --t) {
+      Task T{t, C.diag[t], 0, 0};
+      std::vector<std::pair<int, int>> pp;
+      int l = 0;
+      for (int q = C.row_ptr[t]; q < C.row_ptr[t + 1]; ++q)
+        if (C.col[q] > t) {
+          pp.push_back({q, C.col[q]});
+          l = std::max(l, lv[C.col[q]]);
+        }
+      lv[t] = l + 1;
+      tk.push_back({l + 1, T});
+      prs.push_back(pp);
+    }
+    std::vector<int> idx(tk.size());
+    std::iota(idx.begin(), idx.end(), 0);
+    std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) { return tk[a].first < tk[b].first; });
+    int L = tk.empty() ? 0 : tk[idx.back()].first;
+    C.bwd_level_ptr.assign(L + 1, 0);
+    for (int a : idx) {
+      Task T = tk[a].second;
+      T.pbeg = (int)C.bwd_pa.size();
+      for (auto& pr : prs[a]) {
+        C.bwd_pa.push_back(pr.first);
+        C.bwd_pb.push_back(pr.second);
+      }
+      T.pend = (int)C.bwd_pa.size();
+      C.bwd_tasks.push_back(T);
+      C.bwd_level_ptr[tk[a].first]++;
+    }
+    for (int l = 1; l <= L; ++l) C.bwd_level_ptr[l] += C.bwd_level_ptr[l - 1];
+  }
+  return "";
+}
+
+WaveSchedule build_wave_schedule(const std::vector<Task>& tasks,
+                                 const std::vector<int>& level_ptr, int width) {
+  WaveSchedule ws;
+  ws.width = width;
+  const int L = (int)level_ptr.size() - 1;
+  ws.level_pass.assign(L + 1, 0);
+  int passes = 0;
+  for (int l = 0; l < L; ++l) {
+    std::vector<int> ids;
+    for (int q = level_ptr[l]; q < level_ptr[l + 1]; ++q) ids.push_back(q);
+    std::stable_sort(ids.begin(), ids.end(), [&](int a, int b) {
+      return (tasks[a].pend - tasks[a].pbeg) > (tasks[b].pend - tasks[b].pbeg);
+    });
+    std::vector<std::vector<int>> lane(width);
+    std::vector<long long> load(width, 0);
+    for (int id : ids) {
+      int best = 0;
+      for (int w = 1; w < width; ++w)
+        if (load[w] < load[best] || (load[w] == load[best] && lane[w].size() < lane[best].size()))
+          best = w;
+      lane[best].push_back(id);
+      load[best] += 1 + (tasks[id].pend - tasks[id].pbeg);
+    }
+    size_t np = 0;
+    for (auto& v : lane) np = std::max(np, v.size());
+    for (size_t p = 0; p < np; ++p)
+      for (int w = 0; w < width; ++w)
+        ws.tasks.push_back(p < lane[w].size() ? tasks[lane[w][p]] : Task{-1, -1, 0, 0});
+    passes += (int)np;
+    ws.level_pass[l + 1] = passes;
+  }
+  return ws;
+}
+
+}  // namespace camp

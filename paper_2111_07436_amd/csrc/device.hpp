@@ -1,0 +1,168 @@
+// Device-side view of a compiled mechanism and helpers shared by every engine.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace camp {
+
+constexpr int kWave = 64;
+constexpr int kMaxOrder = 5;
+constexpr int kHist = kMaxOrder + 3;   // backward differences D[0..q+2]
+
+// Level-scheduled task (see mech.hpp Task).
+struct alignas(16) DTask {
+  int dst, diag, pbeg, pend;
+};
+
+// Device copies of the compiled tables; passed to kernels by value.
+struct DevMech {
+  int N, R, Z, n_inst, n_ext, n_part, n_gas;
+  int lu_levels, fwd_levels, bwd_levels;
+  // rate constants
+  const int* rs_kind;
+  const int* rs_ext;
+  const int* rs_inst;
+  const int* rs_nr;
+  const double* rs_v;          // [R * 12]
+  // reactions
+  const int* rx_react;         // [R * 3], -1 padded, elimination positions
+  const int* rx_pofs;          // [R + 1]
+  // forcing terms per species
+  const int* term_ptr;
+  const int* term_rxn;
+  const double* term_coef;
+  // Jacobian contributions per slot
+  const int* jc_ptr;
+  const int* jc_part;
+  const double* jc_coef;
+  const uint8_t* is_diag;      // [Z]
+  const int* diag;             // [N]
+  const int* perm;             // [N] user state index at elimination position t
+  // sequential (level-ordered) tasks
+  const DTask* lu_task;  int n_lu_task;
+  const DTask* fwd_task; int n_fwd_task;
+  const DTask* bwd_task; int n_bwd_task;
+  const int2* lu_pair;         // (pa, pb)
+  const int2* fwd_pair;
+  const int2* bwd_pair;
+  // wavefront schedules: per level, passes of 64 lane-tasks
+  const DTask* wlu;  const int* wlu_lp;
+  const DTask* wfwd; const int* wfwd_lp;
+  const DTask* wbwd; const int* wbwd_lp;
+};
+
+// Per-cell environment (device pointers, row-major [cells] / [cells][n_inst]).
+struct DevEnv {
+  const double* T;
+  const double* P;
+  const double* cos_sza;       // may be null
+  const double* radius;        // may be null when n_inst == 0
+  const double* mass;
+  const double* override_;     // may be null
+};
+
+struct SolveParams {
+  double dt, rtol, atol, h_min, h_init, newton_tol;
+  int max_order, max_steps, newton_maxit;
+};
+
+// BDF coefficients: gamma_q = sum_{j=1}^{q} 1/j; local error constant 1/(q+1).
+__device__ __forceinline__ double bdf_gamma(int q) {
+  double g = 0.0;
+  for (int j = 1; j <= q; ++j) g += 1.0 / j;
+  return g;
+}
+
+constexpr double kGasConstant = 8.314462618;  // J mol^-1 K^-1
+constexpr double kAtmPa = 101325.0;
+constexpr double kPi = 3.14159265358979323846;
+
+// Rate constant of expanded reaction `r` for one cell (paper table of Process classes).
+// Phase-instance rates are zero when the instance has no mass.
+__device__ inline double rate_constant(const DevMech& m, int r, double T, double P, double cosz,
+                                       const double* radius, const double* mass,
+                                       const double* ovr) {
+  const int kind = m.rs_kind[r];
+  const double* v = m.rs_v + (size_t)r * 12;
+  switch (kind) {
+    case 1: {  // Arrhenius, already scaled to mol m^-3 units
+      double k = v[0] * exp(-v[1] / T);
+      if (v[2] != 0.0) k *= pow(T / v[3], v[2]);
+      if (v[4] != 0.0) k *= 1.0 + v[4] * P;
+      return k;
+    }
+    case 2: {  // photolysis
+      int e = m.rs_ext[r];
+      if (ovr) return ovr[e];
+      return v[1] != 0.0 ? v[0] * fmax(0.0, cosz) : v[0];
+    }
+    case 3:
+    case 4: {  // emission, first-order loss
+      int e = m.rs_ext[r];
+      return ovr ? ovr[e] : v[0];
+    }
+    default:
+      break;
+  }
+  const int g = m.rs_inst[r];
+  const double ms = mass[g];
+  if (ms == 0.0) return 0.0;
+  if (kind == 5) {  // condensed-phase Arrhenius
+    double k = v[0] * exp(-v[1] / T);
+    if (v[2] != 0.0) k *= pow(T / v[3], v[2]);
+    if (v[4] != 0.0) k *= 1.0 + v[4] * P;
+    if (v[5] != 0.0) {
+      const int nr = m.rs_nr[r];
+      const double vol = ms / v[6];          // phase volume per air volume
+      if (nr != 1) k *= pow(1000.0 * vol, (double)(1 - nr));
+    }
+    return k;
+  }
+  // phase transfer: v = {D_g, MW_g, alpha, density, mw_abs, p0..p3}
+  const double rad = radius[g];
+  const double Dg = v[0], mw = v[1], alpha = v[2], rho = v[3];
+  const double c_bar = sqrt(8.0 * kGasConstant * T / (kPi * mw));
+  const double Kn = 3.0 * Dg / c_bar / rad;
+  const double ffs = 0.75 * alpha * (1.0 + Kn) / (Kn * Kn + Kn + 0.283 * Kn * alpha + 0.75 * alpha);
+  const double n_part = ms / (rho * (4.0 / 3.0) * kPi * rad * rad * rad);
+  const double kc = 4.0 * kPi * rad * Dg * ffs * n_part;
+  if (kind == 6 || kind == 8) return kc;
+  if (kind == 7) {  // Henry evaporation
+    const double H = v[5] * exp(v[6] * (1.0 / T - 1.0 / 298.0));
+    return kc / (H * 1000.0 * (ms / rho) * kGasConstant * T);
+  }
+  // SIMPOL evaporation
+  const double p0 = exp10(v[5] / T + v[6] + v[7] * T + v[8] * log(T));
+  const double n_abs = ms / v[4];
+  return kc * p0 * kAtmPa / (kGasConstant * T * n_abs);
+}
+
+// Sum over the 64 lanes of a wavefront; every lane receives the same value.
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, kWave);
+  return v;
+}
+
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v = fmax(v, __shfl_xor(v, o, kWave));
+  return v;
+}
+
+__device__ __forceinline__ int wave_or(int v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v |= __shfl_xor(v, o, kWave);
+  return v;
+}
+
+// Cell-interleaved slab addressing: element x (of X per cell) of cell c lives at
+// ((c / 64) * X + x) * 64 + c % 64, so the 64 lanes of a wavefront touching the same x of
+// 64 consecutive cells read one contiguous 512-byte line.
+__device__ __forceinline__ size_t slab(int c, int X) {
+  return ((size_t)(c >> 6) * X) * kWave + (c & 63);
+}
+
+}  // namespace camp

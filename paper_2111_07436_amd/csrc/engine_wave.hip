@@ -1,0 +1,630 @@
+// Fused persistent engine, one wavefront per cell.
+//
+// Every cell's whole integration over the host step (rate constants, then BDF steps with
+// forcing, Newton matrix, sparse LU and triangular solves, error test and step/order
+// control) runs inside one kernel. A wavefront owns one cell at a time: its Newton matrix,
+// state, right-hand side, rates and partial derivatives live in LDS, and its BDF history
+// lives in registers with species t held by lane t % 64. Sparse work is spread over the
+// 64 lanes by the level-scheduled tables built on the host: every task of one dependency
+// level runs in parallel, levels are separated by a workgroup barrier. Control decisions
+// use wavefront reductions, so they are uniform and need no masking. When a cell is done
+// the wavefront takes the next one from a device-side queue (or from the grid index).
+//
+// Forcing and Jacobian (paper Sect. 2.4.2): f_i = sum_k S_ik r_k and
+// J_ij = sum_k S_ik dr_k/dy_j, with r_k = k_k prod y over reactant occurrences.
+#include "bdf_common.hpp"
+#include "camp.h"
+
+namespace camp {
+
+namespace {
+
+template <int NPL>
+struct WaveCell {
+  const DevMech& m;
+  double* M;
+  double* yl;
+  double* xl;
+  double* P;
+  double* kc;
+  int lane;
+
+  __device__ double wrms(const double (&v)[NPL], const double (&w)[NPL]) const {
+    double s = 0.0;
+#pragma unroll
+    for (int i = 0; i < NPL; ++i)
+      if (lane + kWave * i < m.N) {
+        double a = v[i] * w[i];
+        s += a * a;
+      }
+    return sqrt(wave_sum(s) / m.N);
+  }
+
+  // P[k] = r_k from yl; then f for owned species. yl must be visible to all lanes.
+  __device__ void forcing(double (&f)[NPL]) const {
+    for (int k = lane; k < m.R; k += kWave) {
+      const int* rr = m.rx_react + 3 * k;
+      double r = kc[k];
+      int a = rr[0], b = rr[1], c = rr[2];
+      if (a >= 0) r *= yl[a];
+      if (b >= 0) r *= yl[b];
+      if (c >= 0) r *= yl[c];
+      P[k] = r;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < NPL; ++i) {
+      const int t = lane + kWave * i;
+      double acc = 0.0;
+      if (t < m.N)
+        for (int q = m.term_ptr[t]; q < m.term_ptr[t + 1]; ++q) acc += m.term_coef[q] * P[m.term_rxn[q]];
+      f[i] = acc;
+    }
+    __syncthreads();
+  }
+
+  // M = I - c J(yl) in the filled pattern (fill slots 0 off the diagonal).
+  __device__ void newton_matrix(double c) const {
+    for (int k = lane; k < m.R; k += kWave) {
+      const int* rr = m.rx_react + 3 * k;
+      const int a = rr[0], b = rr[1], cc = rr[2];
+      const double kk = kc[k];
+      const int base = m.rx_pofs[k];
+      const double ya = a >= 0 ? yl[a] : 1.0, yb = b >= 0 ? yl[b] : 1.0, yc = cc >= 0 ? yl[cc] : 1.0;
+      if (a >= 0) P[base] = kk * yb * yc;
+      if (b >= 0) P[base + 1] = kk * ya * yc;
+      if (cc >= 0) P[base + 2] = kk * ya * yb;
+    }
+    __syncthreads();
+    for (int s = lane; s < m.Z; s += kWave) {
+      double acc = 0.0;
+      for (int q = m.jc_ptr[s]; q < m.jc_ptr[s + 1]; ++q) acc += m.jc_coef[q] * P[m.jc_part[q]];
+      M[s] = (m.is_diag[s] ? 1.0 : 0.0) - c * acc;
+    }
+    __syncthreads();
+  }
+
+  // In-place LU of M, one dependency level at a time. Returns 0 if a pivot is not a
+  // finite nonzero.
+  __device__ int lu() const {
+    for (int l = 0; l < m.lu_levels; ++l) {
+      for (int p = m.wlu_lp[l]; p < m.wlu_lp[l + 1]; ++p) {
+        const DTask t = m.wlu[p * kWave + lane];
+        if (t.dst >= 0) {
+          double acc = M[t.dst];
+          for (int q = t.pbeg; q < t.pend; ++q) {
+            const int2 pr = m.lu_pair[q];
+            acc -= M[pr.x] * M[pr.y];
+          }
+          if (t.diag >= 0) acc /= M[t.diag];
+          M[t.dst] = acc;
+        }
+      }
+      __syncthreads();
+    }
+    int bad = 0;
+    for (int t = lane; t < m.N; t += kWave) {
+      const double u = M[m.diag[t]];
+      if (!(fabs(u) > 0.0) || !isfinite(u)) bad = 1;
+    }
+    return !wave_or(bad);
+  }
+
+  __device__ int newton_matrix_lu(double c) const {
+    newton_matrix(c);
+    return lu();
+  }
+
+  // xl <- (LU)^-1 xl
+  __device__ void solve() const {
+    for (int l = 0; l < m.fwd_levels; ++l) {
+      for (int p = m.wfwd_lp[l]; p < m.wfwd_lp[l + 1]; ++p) {
+        const DTask t = m.wfwd[p * kWave + lane];
+        if (t.dst >= 0) {
+          double acc = xl[t.dst];
+          for (int q = t.pbeg; q < t.pend; ++q) {
+            const int2 pr = m.fwd_pair[q];
+            acc -= M[pr.x] * xl[pr.y];
+          }
+          xl[t.dst] = acc;
+        }
+      }
+      __syncthreads();
+    }
+    for (int l = 0; l < m.bwd_levels; ++l) {
+      for (int p = m.wbwd_lp[l]; p < m.wbwd_lp[l + 1]; ++p) {
+        const DTask t = m.wbwd[p * kWave + lane];
+        if (t.dst >= 0) {
+          double acc = xl[t.dst];
+          for (int q = t.pbeg; q < t.pend; ++q) {
+            const int2 pr = m.bwd_pair[q];
+            acc -= M[pr.x] * xl[pr.y];
+          }
+          xl[t.dst] = acc / M[t.diag];
+        }
+      }
+      __syncthreads();
+    }
+  }
+};
+
+// D[j] <- sum_k T[j][k] D[k] for j, k <= q (T from rescale_matrix, q-independent block).
+template <int NPL>
+__device__ __forceinline__ void rescale_hist(double (&D)[kHist][NPL], int q, double rho) {
+  double T[kMaxOrder + 1][kMaxOrder + 1];
+  rescale_matrix(kMaxOrder, rho, T);
+#pragma unroll
+  for (int i = 0; i < NPL; ++i) {
+    double nd[kMaxOrder + 1];
+#pragma unroll
+    for (int j = 0; j <= kMaxOrder; ++j) {
+      double s = 0.0;
+#pragma unroll
+      for (int k = 0; k <= kMaxOrder; ++k)
+        if (k <= q) s += T[j][k] * D[k][i];
+      nd[j] = s;
+    }
+#pragma unroll
+    for (int j = 1; j <= kMaxOrder; ++j)
+      if (j <= q) D[j][i] = nd[j];
+  }
+}
+
+template <int NPL>
+__device__ void solve_one_cell(const DevMech& m, const DevEnv& env, double* state, int cell,
+                               const SolveParams& sp, int* status_out, camp_cell_stats* stats_out,
+                               WaveCell<NPL>& W) {
+  const int lane = W.lane;
+  const int N = m.N;
+  camp_cell_stats cs = {0, 0, 0, 0, 0, 0, 0, 0};
+  int status = ST_OK;
+
+  // ---- rate constants (fixed over the host step) ----
+  const double Tk = env.T[cell], Pp = env.P[cell];
+  const double cz = env.cos_sza ? env.cos_sza[cell] : 1.0;
+  const double* rad = env.radius ? env.radius + (size_t)cell * m.n_inst : nullptr;
+  const double* mas = env.mass ? env.mass + (size_t)cell * m.n_inst : nullptr;
+  const double* ovr = env.override_ ? env.override_ + (size_t)cell * m.n_ext : nullptr;
+  int bad = 0;
+  for (int k = lane; k < m.R; k += kWave) {
+    const double v = rate_constant(m, k, Tk, Pp, cz, rad, mas, ovr);
+    W.kc[k] = v;
+    if (!isfinite(v)) bad = 1;
+  }
+
+  // ---- initial state ----
+  double D[kHist][NPL];
+  double* yrow = state + (size_t)cell * N;
+#pragma unroll
+  for (int i = 0; i < NPL; ++i) {
+    const int t = lane + kWave * i;
+    const double v = t < N ? yrow[m.perm[t]] : 0.0;
+    if (t < N) {
+      W.yl[t] = v;
+      if (!isfinite(v)) bad = 1;
+    }
+    D[0][i] = v;
+#pragma unroll
+    for (int j = 1; j < kHist; ++j) D[j][i] = 0.0;
+  }
+  __syncthreads();
+  if (wave_or(bad)) {
+    status = ST_NONFINITE;
+  }
+
+  const double span = sp.dt;
+  double w[NPL], f0[NPL], d[NPL];
+  if (status == ST_OK) {
+    W.forcing(f0);
+    cs.n_f++;
+    int nf = 0;
+#pragma unroll
+    for (int i = 0; i < NPL; ++i) {
+      if (!isfinite(f0[i])) nf = 1;
+      const double s = sp.atol + sp.rtol * fabs(D[0][i]);
+      w[i] = s > 0.0 ? 1.0 / s : 0.0;
+    }
+    if (wave_or(nf)) status = ST_NONFINITE;
+  }
+  double h = 0.0;
+  if (status == ST_OK) {
+    // starting step
+    const double d0 = W.wrms(D[0], w), d1 = W.wrms(f0, w);
+    const double h0 = starting_step_h0(d0, d1, span);
+#pragma unroll
+    for (int i = 0; i < NPL; ++i) {
+      const int t = lane + kWave * i;
+      if (t < N) W.yl[t] = D[0][i] + h0 * f0[i];
+    }
+    __syncthreads();
+    double f1[NPL];
+    W.forcing(f1);
+    cs.n_f++;
+#pragma unroll
+    for (int i = 0; i < NPL; ++i) f1[i] -= f0[i];
+    const double d2 = W.wrms(f1, w) / h0;
+    h = sp.h_init > 0.0 ? fmin(sp.h_init, span) : starting_step(h0, d1, d2, span);
+#pragma unroll
+    for (int i = 0; i < NPL; ++i) D[1][i] = h * f0[i];
+  }
+
+  int q = 1, n_equal = 0, attempts = 0, lu_valid = 0, lu_age = 0;
+  double t = 0.0, c_lu = 0.0, crate = 1.0, err = 0.0;
+  while (status == ST_OK && t < span) {
+    if (span - (t + h) <= 1e-12 * span) {
+      const double rho = (span - t) / h;
+      if (rho != 1.0) {
+        rescale_hist(D, q, rho);
+        h = span - t;
+        n_equal = 0;
+      }
+    }
+    int nfw = 0;
+#pragma unroll
+    for (int i = 0; i < NPL; ++i) {
+      w[i] = 1.0 / (sp.rtol * fabs(D[0][i]) + sp.atol);
+      if (lane + kWave * i < N && !isfinite(w[i])) nfw = 1;
+    }
+    if (wave_or(nfw)) {
+      status = ST_NONFINITE;
+      break;
+    }
+    int consec_err = 0, consec_nf = 0, force_lu = 0;
+    bool accepted = false;
+    while (true) {
+      if (++attempts > sp.max_steps) { status = ST_MAX_STEPS; break; }
+      if (h < sp.h_min) { status = ST_H_MIN; break; }
+      double gq = bdf_gamma(q);
+      const double c = h / gq;
+      double yp[NPL], psi[NPL], yv[NPL];
+#pragma unroll
+      for (int i = 0; i < NPL; ++i) {
+        double s = D[0][i], ps = 0.0, g = 0.0;
+#pragma unroll
+        for (int j = 1; j <= kMaxOrder; ++j) {
+          g += 1.0 / j;
+          if (j <= q) {
+            s += D[j][i];
+            ps += g * D[j][i];
+          }
+        }
+        yp[i] = s;
+        psi[i] = ps / gq;
+        yv[i] = s;
+        d[i] = 0.0;
+        const int tt = lane + kWave * i;
+        if (tt < N) W.yl[tt] = s;
+      }
+      __syncthreads();
+      int fresh = 0, lu_ok = 1;
+      if (force_lu || !lu_valid || fabs(c / c_lu - 1.0) > kLuGammaDrift || lu_age >= kLuMaxAge) {
+        lu_ok = W.newton_matrix_lu(c);
+        cs.n_jac++;
+        cs.n_lu++;
+        lu_valid = lu_ok;
+        c_lu = c;
+        lu_age = 0;
+        crate = 1.0;
+        fresh = 1;
+      }
+      bool conv = false;
+      int nonfin = 0;
+      if (lu_ok) {
+        const double scale = (c == c_lu) ? 1.0 : 2.0 / (1.0 + c / c_lu);
+        double dn_old = 0.0;
+        for (int it = 0; it < sp.newton_maxit; ++it) {
+          if (it > 0) {
+#pragma unroll
+            for (int i = 0; i < NPL; ++i) {
+              const int tt = lane + kWave * i;
+              if (tt < N) W.yl[tt] = yv[i];
+            }
+            __syncthreads();
+          }
+          double f[NPL];
+          W.forcing(f);
+          cs.n_f++;
+          int nf = 0;
+#pragma unroll
+          for (int i = 0; i < NPL; ++i) {
+            const int tt = lane + kWave * i;
+            if (tt < N) {
+              if (!isfinite(f[i])) nf = 1;
+              W.xl[tt] = c * f[i] - psi[i] - d[i];
+            }
+          }
+          if (wave_or(nf)) { nonfin = 1; break; }
+          __syncthreads();
+          W.solve();
+          double dl[NPL];
+#pragma unroll
+          for (int i = 0; i < NPL; ++i) {
+            const int tt = lane + kWave * i;
+            dl[i] = tt < N ? W.xl[tt] * scale : 0.0;
+          }
+          __syncthreads();
+          const double dn = W.wrms(dl, w);
+          cs.newton_iters++;
+#pragma unroll
+          for (int i = 0; i < NPL; ++i) {
+            yv[i] += dl[i];
+            d[i] += dl[i];
+          }
+          if (!isfinite(dn)) break;
+          if (it > 0) crate = fmax(0.3 * crate, dn / dn_old);
+          const double dcon = dn * fmin(1.0, crate) / sp.newton_tol;
+          if (dcon <= 1.0) { conv = true; break; }
+          if (it > 0 && dn > kNewtonDiverge * dn_old) break;
+          dn_old = dn;
+        }
+      }
+      if (nonfin) { status = ST_NONFINITE; break; }
+      if (!conv) {
+        if (!fresh && lu_ok) { force_lu = 1; continue; }
+        cs.newton_fail++;
+        if (++consec_nf >= kMaxConsecFail) { status = ST_NEWTON_FAIL; break; }
+        rescale_hist(D, q, 0.25);
+        h *= 0.25;
+        n_equal = 0;
+        force_lu = 0;
+        continue;
+      }
+      force_lu = 0;
+      double dq1[NPL];
+#pragma unroll
+      for (int i = 0; i < NPL; ++i) dq1[i] = d[i] / (q + 1);
+      err = W.wrms(dq1, w);
+      if (err > 1.0) {
+        cs.rejected++;
+        if (++consec_err >= kMaxConsecFail) { status = ST_ERR_FAIL; break; }
+        n_equal = 0;
+        if (consec_err >= kErrRestart) {
+          // restart at order 1 from y_n with a much smaller step: D[1] = h f(y_n)
+#pragma unroll
+          for (int i = 0; i < NPL; ++i) {
+            const int tt = lane + kWave * i;
+            if (tt < N) W.yl[tt] = D[0][i];
+          }
+          __syncthreads();
+          double fn[NPL];
+          W.forcing(fn);
+          cs.n_f++;
+          h *= kRestartFactor;
+          q = 1;
+#pragma unroll
+          for (int i = 0; i < NPL; ++i) {
+            D[1][i] = h * fn[i];
+#pragma unroll
+            for (int j = 2; j < kHist; ++j) D[j][i] = 0.0;
+          }
+          continue;
+        }
+        double rho = fmax(kMinFactor, kSafety * pow(err, -1.0 / (q + 1)));
+        if (consec_err >= 2) rho = fmin(rho, kMinFactor);
+        rescale_hist(D, q, rho);
+        h *= rho;
+        continue;
+      }
+      accepted = true;
+      break;
+    }
+    if (!accepted) break;
+
+    // ---- accept: advance time and update the differences ----
+    cs.steps++;
+    lu_age++;
+    t = (span - (t + h) <= 1e-12 * span) ? span : t + h;
+    n_equal++;
+#pragma unroll
+    for (int i = 0; i < NPL; ++i) {
+      double old_q1 = 0.0;
+#pragma unroll
+      for (int j = 1; j < kHist; ++j)
+        if (j == q + 1) old_q1 = D[j][i];
+      double s = d[i];
+#pragma unroll
+      for (int j = kMaxOrder; j >= 0; --j)
+        if (j <= q) {
+          s += D[j][i];
+          D[j][i] = s;
+        }
+#pragma unroll
+      for (int j = 1; j < kHist; ++j) {
+        if (j == q + 1) D[j][i] = d[i];
+        if (j == q + 2) D[j][i] = d[i] - old_q1;
+      }
+    }
+    if (t >= span) break;
+    if (n_equal < q + 1) continue;
+    double vm[NPL], vp[NPL];
+#pragma unroll
+    for (int i = 0; i < NPL; ++i) {
+      vm[i] = 0.0;
+      vp[i] = 0.0;
+#pragma unroll
+      for (int j = 1; j < kHist; ++j) {
+        if (j == q) vm[i] = D[j][i];
+        if (j == q + 2) vp[i] = D[j][i];
+      }
+    }
+    const double err_m = q > 1 ? W.wrms(vm, w) / q : 0.0;
+    const double err_p = q < sp.max_order ? W.wrms(vp, w) / (q + 2) : 0.0;
+    double rho;
+    q = choose_order(q, sp.max_order, err, err_m, err_p, &rho);
+    rescale_hist(D, q, rho);
+    h *= rho;
+    n_equal = 0;
+  }
+
+  if (status == ST_OK) {
+#pragma unroll
+    for (int i = 0; i < NPL; ++i) {
+      const int tt = lane + kWave * i;
+      if (tt < N) yrow[m.perm[tt]] = D[0][i];
+    }
+  }
+  cs.order = q;
+  if (lane == 0) {
+    status_out[cell] = status;
+    if (stats_out) stats_out[cell] = cs;
+  }
+  __syncthreads();
+}
+
+}  // namespace
+
+// One wavefront per workgroup. queue != nullptr: persistent grid pulling cells from the
+// counter; else cell = blockIdx.x.
+template <int NPL>
+__global__ __launch_bounds__(kWave) void bdf_wave_kernel(DevMech m, DevEnv env, double* state,
+                                                        int n_cells, SolveParams sp, int* status,
+                                                        camp_cell_stats* stats, int* queue) {
+  extern __shared__ double lds[];
+  const int np = m.n_part > m.R ? m.n_part : m.R;
+  WaveCell<NPL> W{m, lds, lds + m.Z, lds + m.Z + m.N, lds + m.Z + 2 * m.N,
+                  lds + m.Z + 2 * m.N + np, (int)threadIdx.x};
+  if (!queue) {
+    const int cell = blockIdx.x;
+    if (cell < n_cells) solve_one_cell<NPL>(m, env, state, cell, sp, status, stats, W);
+    return;
+  }
+  while (true) {
+    int cell = 0;
+    if (threadIdx.x == 0) cell = atomicAdd(queue, 1);
+    cell = __shfl(cell, 0, kWave);
+    if (cell >= n_cells) break;
+    solve_one_cell<NPL>(m, env, state, cell, sp, status, stats, W);
+  }
+}
+
+// ---------------------------------------------------------------- single-step kernels
+// One wavefront per cell; the same device code as the fused engine, on row-major
+// [cells][...] arrays in user state order.
+
+template <int NPL>
+__global__ __launch_bounds__(kWave) void wave_step_kernel(DevMech m, int op, int n_cells,
+                                                          const double* kin, const double* yin,
+                                                          double* out, double gamma) {
+  extern __shared__ double lds[];
+  const int np = m.n_part > m.R ? m.n_part : m.R;
+  WaveCell<NPL> W{m, lds, lds + m.Z, lds + m.Z + m.N, lds + m.Z + 2 * m.N,
+                  lds + m.Z + 2 * m.N + np, (int)threadIdx.x};
+  const int cell = blockIdx.x;
+  if (cell >= n_cells) return;
+  const int lane = threadIdx.x;
+  if (op == 0 || op == 1) {  // forcing / Newton matrix from k and y
+    for (int k = lane; k < m.R; k += kWave) W.kc[k] = kin[(size_t)cell * m.R + k];
+    for (int t = lane; t < m.N; t += kWave) W.yl[t] = yin[(size_t)cell * m.N + m.perm[t]];
+    __syncthreads();
+    if (op == 0) {
+      double f[NPL];
+      W.forcing(f);
+#pragma unroll
+      for (int i = 0; i < NPL; ++i) {
+        const int t = lane + kWave * i;
+        if (t < m.N) out[(size_t)cell * m.N + m.perm[t]] = f[i];
+      }
+    } else {
+      W.newton_matrix(gamma);
+      for (int s = lane; s < m.Z; s += kWave) out[(size_t)cell * m.Z + s] = W.M[s];
+    }
+  } else if (op == 2) {      // LU in place on out
+    for (int s = lane; s < m.Z; s += kWave) W.M[s] = out[(size_t)cell * m.Z + s];
+    __syncthreads();
+    W.lu();
+    for (int s = lane; s < m.Z; s += kWave) out[(size_t)cell * m.Z + s] = W.M[s];
+  } else {                   // solve: kin = LU, out = b -> x
+    for (int s = lane; s < m.Z; s += kWave) W.M[s] = kin[(size_t)cell * m.Z + s];
+    for (int t = lane; t < m.N; t += kWave) W.xl[t] = out[(size_t)cell * m.N + m.perm[t]];
+    __syncthreads();
+    W.solve();
+    for (int t = lane; t < m.N; t += kWave) out[(size_t)cell * m.N + m.perm[t]] = W.xl[t];
+  }
+}
+
+__global__ void rates_step_kernel(DevMech m, DevEnv env, int n_cells, double* k_out) {
+  const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (long long)n_cells * m.R) return;
+  const int cell = (int)(idx / m.R), r = (int)(idx % m.R);
+  const double* rad = env.radius ? env.radius + (size_t)cell * m.n_inst : nullptr;
+  const double* mas = env.mass ? env.mass + (size_t)cell * m.n_inst : nullptr;
+  const double* ovr = env.override_ ? env.override_ + (size_t)cell * m.n_ext : nullptr;
+  k_out[idx] = rate_constant(m, r, env.T[cell], env.P[cell], env.cos_sza ? env.cos_sza[cell] : 1.0,
+                             rad, mas, ovr);
+}
+
+hipError_t launch_rates_step(const DevMech& m, const DevEnv& env, int n_cells, double* k_out,
+                             hipStream_t stream) {
+  const long long n = (long long)n_cells * m.R;
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(rates_step_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, m,
+                     env, n_cells, k_out);
+  return hipGetLastError();
+}
+
+size_t wave_lds_bytes(const DevMech& m) {
+  const int np = m.n_part > m.R ? m.n_part : m.R;
+  return sizeof(double) * ((size_t)m.Z + 2 * (size_t)m.N + np + m.R);
+}
+
+hipError_t launch_bdf_wave(const DevMech& m, const DevEnv& env, double* state, int n_cells,
+                           const SolveParams& sp, int* status, camp_cell_stats* stats, int* queue,
+                           int grid, hipStream_t stream) {
+  const size_t lds = wave_lds_bytes(m);
+  const int npl = (m.N + kWave - 1) / kWave;
+#define CAMP_WAVE_CASE(K)                                                                      \
+  case K: {                                                                                    \
+    hipError_t e = hipFuncSetAttribute((const void*)bdf_wave_kernel<K>,                        \
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);   \
+    if (e != hipSuccess) return e;                                                             \
+    hipLaunchKernelGGL(bdf_wave_kernel<K>, dim3(grid), dim3(kWave), lds, stream, m, env, state, \
+                       n_cells, sp, status, stats, queue);                                     \
+    return hipGetLastError();                                                                  \
+  }
+  switch (npl) {
+    CAMP_WAVE_CASE(1)
+    CAMP_WAVE_CASE(2)
+    CAMP_WAVE_CASE(3)
+    CAMP_WAVE_CASE(4)
+    CAMP_WAVE_CASE(5)
+    CAMP_WAVE_CASE(6)
+    CAMP_WAVE_CASE(7)
+    CAMP_WAVE_CASE(8)
+    CAMP_WAVE_CASE(9)
+    default:
+      return hipErrorInvalidValue;
+  }
+#undef CAMP_WAVE_CASE
+}
+
+hipError_t launch_wave_step(const DevMech& m, int op, int n_cells, const double* kin,
+                            const double* yin, double* out, double gamma, hipStream_t stream) {
+  const size_t lds = wave_lds_bytes(m);
+  const int npl = (m.N + kWave - 1) / kWave;
+  if (n_cells == 0) return hipSuccess;
+#define CAMP_STEP_CASE(K)                                                                      \
+  case K: {                                                                                    \
+    hipError_t e = hipFuncSetAttribute((const void*)wave_step_kernel<K>,                       \
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);   \
+    if (e != hipSuccess) return e;                                                             \
+    hipLaunchKernelGGL(wave_step_kernel<K>, dim3(n_cells), dim3(kWave), lds, stream, m, op,     \
+                       n_cells, kin, yin, out, gamma);                                         \
+    return hipGetLastError();                                                                  \
+  }
+  switch (npl) {
+    CAMP_STEP_CASE(1)
+    CAMP_STEP_CASE(2)
+    CAMP_STEP_CASE(3)
+    CAMP_STEP_CASE(4)
+    CAMP_STEP_CASE(5)
+    CAMP_STEP_CASE(6)
+    CAMP_STEP_CASE(7)
+    CAMP_STEP_CASE(8)
+    CAMP_STEP_CASE(9)
+    default:
+      return hipErrorInvalidValue;
+  }
+#undef CAMP_STEP_CASE
+}
+
+}  // namespace camp

@@ -1,0 +1,110 @@
+// Host-side compiled mechanism: expansion, elimination order, symbolic fill and the
+// level-scheduled tables that every device engine reads. Pure C++ (no HIP types), so the
+// compiler can be built and checked on a machine without a GPU.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "camp.h"
+
+namespace camp {
+
+// Kind of rate constant carried by one expanded (generalized mass-action) reaction.
+enum RateKind : int {
+  KR_ARRHENIUS = 1,
+  KR_PHOTOLYSIS = 2,
+  KR_EMISSION = 3,
+  KR_LOSS = 4,
+  KR_CONDENSED = 5,
+  KR_HENRY_COND = 6,
+  KR_HENRY_EVAP = 7,
+  KR_SIMPOL_COND = 8,
+  KR_SIMPOL_EVAP = 9
+};
+
+constexpr int kRateParams = 12;
+
+// Parameter block of one expanded reaction, laid out for the rate-constant kernel.
+//   ARRHENIUS : v = {A * (N_A 1e-6)^(n_r-1), Ea/kb, B, D, E}
+//   PHOTOLYSIS: v = {J0, sza_flag}
+//   EMISSION  : v = {E};  LOSS: v = {k}
+//   CONDENSED : v = {A, Ea/kb, B, D, E, aqueous, density}
+//   *_COND/*_EVAP: v = {D_g, MW_g, alpha, density, mw_absorber, p0..p3}
+//                  Henry p = {H298, C}, SIMPOL p = {B1, B2, B3, B4}
+struct RateSpec {
+  int kind;
+  int ext;    // column of rate_override, or -1
+  int inst;   // global phase-instance index, or -1
+  int nr;     // reactant occurrences
+  double v[kRateParams];
+};
+
+// One unit of level-scheduled work shared by the LU factorization and the triangular
+// solves: value[dst] = (value[dst] - sum_{q in [pbeg, pend)} A[pa[q]] * B[pb[q]]) / A[diag]
+// (no division when diag < 0).
+struct Task {
+  int dst, diag, pbeg, pend;
+};
+
+// Tasks of one dependency level, grouped in passes of `width` lanes each: the lane l task
+// of pass p is tasks[(pass_begin + p) * width + l] (dst < 0: idle lane).
+struct WaveSchedule {
+  int width = 0;
+  std::vector<int> level_pass;   // [levels + 1] pass offsets
+  std::vector<Task> tasks;       // [passes * width]
+};
+
+struct Compiled {
+  // sizes
+  int n_state = 0, n_gas = 0, n_inst = 0, n_rxn = 0, n_ext = 0;
+  int nnz0 = 0, nnz = 0;
+  long long lu_pairs = 0;
+
+  // phase instance -> phase, first state index (user order)
+  std::vector<int> inst_phase, inst_base;
+  // elimination order: perm[t] = user state index at position t; iperm is its inverse
+  std::vector<int> perm, iperm;
+
+  // expanded reactions (device state indices, i.e. elimination positions)
+  std::vector<RateSpec> rate;           // [R]
+  std::vector<int> rx_react;            // [R * 3], pad -1
+  std::vector<int> rx_nr;               // [R]
+  std::vector<int> rx_pofs;             // [R + 1] partial offsets
+  int n_partials = 0;
+
+  // forcing: f_t = sum_q term_coef[q] * r[term_rxn[q]], q in [term_ptr[t], term_ptr[t+1])
+  std::vector<int> term_ptr, term_rxn;
+  std::vector<double> term_coef;
+
+  // filled pattern, CSR in elimination order
+  std::vector<int> row_ptr, col, diag;
+  std::vector<char> pattern0;
+
+  // Jacobian: J[s] = sum_q jc_coef[q] * P[jc_part[q]], q in [jc_ptr[s], jc_ptr[s+1])
+  std::vector<int> jc_ptr, jc_part;
+  std::vector<double> jc_coef;
+
+  // LU (Crout, one task per computed entry) and solves, in level order
+  std::vector<Task> lu_tasks, fwd_tasks, bwd_tasks;
+  std::vector<int> lu_level_ptr, fwd_level_ptr, bwd_level_ptr;
+  std::vector<int> lu_pa, lu_pb;        // LU pairs: M[pa] * M[pb]
+  std::vector<int> fwd_pa, fwd_pb;      // forward pairs: M[pa] * x[pb]
+  std::vector<int> bwd_pa, bwd_pb;      // backward pairs: M[pa] * x[pb]
+
+  int lu_levels() const { return (int)lu_level_ptr.size() - 1; }
+  int fwd_levels() const { return (int)fwd_level_ptr.size() - 1; }
+  int bwd_levels() const { return (int)bwd_level_ptr.size() - 1; }
+};
+
+// Returns an empty string on success, else the validation/compile error.
+std::string compile_mechanism(const camp_reaction* rxns, int n_rxn, const camp_species* sp,
+                              int n_sp, const camp_phase* ph, int n_ph, Compiled& out);
+
+// Groups the tasks of each level into passes of `width` lanes, longest task first onto
+// the least-loaded lane, so that each pass's lanes carry similar work.
+WaveSchedule build_wave_schedule(const std::vector<Task>& tasks,
+                                 const std::vector<int>& level_ptr, int width);
+
+}  // namespace camp

@@ -1,0 +1,63 @@
+// Host runtime: mechanism residency on the device, workspaces, engine launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <map>
+#include <mutex>
+#include <string>
+#include <tuple>
+
+#include "camp.h"
+#include "device.hpp"
+#include "mech.hpp"
+
+namespace camp {
+
+struct LaneCtx;
+
+// Tunable launch choice for one (mechanism, cell-count bucket).
+struct Tuning {
+  int engine = CAMP_ENGINE_FUSED_WAVE;
+  int persistent = 1;        // wave engine: 1 = queue-driven persistent grid
+  int grid_mult = 8;         // wave engine: workgroups per CU when persistent
+  double ms = 0.0;           // measured trial time
+};
+
+struct DeviceTables {
+  int device = -1;
+  void* blob = nullptr;
+  size_t bytes = 0;
+  DevMech dm{};
+};
+
+void set_error(const std::string& msg);
+int hip_fail(hipError_t e, const char* what);
+
+// Launchers (defined in the engine files).
+size_t wave_lds_bytes(const DevMech& m);
+hipError_t launch_bdf_wave(const DevMech& m, const DevEnv& env, double* state, int n_cells,
+                           const SolveParams& sp, int* status, camp_cell_stats* stats, int* queue,
+                           int grid, hipStream_t stream);
+hipError_t launch_wave_step(const DevMech& m, int op, int n_cells, const double* kin,
+                            const double* yin, double* out, double gamma, hipStream_t stream);
+hipError_t launch_rates_step(const DevMech& m, const DevEnv& env, int n_cells, double* k_out,
+                             hipStream_t stream);
+hipError_t run_plain(const DevMech& m, const DevEnv& env, double* state, int n_cells,
+                     const SolveParams& sp, int* status, camp_cell_stats* stats, int use_graph,
+                     hipStream_t stream);
+hipError_t run_fused_lane(const DevMech& m, const DevEnv& env, double* state, int n_cells,
+                          const SolveParams& sp, int* status, camp_cell_stats* stats,
+                          int n_slots, hipStream_t stream);
+hipError_t launch_count_failed(int n, const int* status, int* out, hipStream_t stream);
+hipError_t launch_fill_int(int* p, int n, int v, hipStream_t stream);
+
+}  // namespace camp
+
+struct camp_mech {
+  camp::Compiled C;
+  camp::WaveSchedule wlu, wfwd, wbwd;
+  std::mutex mu;
+  std::map<int, camp::DeviceTables> dev;            // per device id
+  std::map<std::pair<int, int>, camp::Tuning> tune; // (device, cell bucket)
+};

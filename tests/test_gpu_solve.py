@@ -1,0 +1,181 @@
+"""End-to-end parity of every engine against the oracle (a2-a8), through the C ABI.
+
+Gate (spec metric, reading C-6 in the design doc): with the GPU at rtol 1e-8 / atol 1e-18
+and the oracle at rtol 1e-10 / atol 1e-20, every species with |y_ref| >= 1e-12 mol m^-3
+agrees to 1e-4 relative and every species below that floor to 1e-12 absolute.
+"""
+import numpy as np
+import pytest
+
+from paper_2111_07436_amd import workloads as W
+from oracle.solve import oracle_solve
+from tests import mechs
+from tests.gpu_util import assert_parity, log, require_gpu
+
+pytestmark = pytest.mark.gpu
+
+GPU_RTOL, GPU_ATOL = 1e-8, 1e-18
+OR_RTOL, OR_ATOL = 1e-10, 1e-20
+ENGINES = ["wave", "lane", "plain"]
+
+
+@pytest.fixture(scope="module")
+def torch():
+    return require_gpu()
+
+
+def gpu_solve(m, wl, engine, rtol=GPU_RTOL, atol=GPU_ATOL, calls=None, **kw):
+    from paper_2111_07436_amd import camp
+    import torch
+    denv = camp.DeviceEnv(wl.env)
+    y = torch.from_numpy(wl.y0.copy()).cuda()
+    status = torch.empty(wl.n_cells, dtype=torch.int32, device="cuda")
+    opts = camp.make_opts(engine=engine, max_steps=kw.pop("max_steps", 20000), **kw)
+    for _ in range(wl.n_calls if calls is None else calls):
+        m.solve_device(denv, y, wl.dt, rtol, atol, opts, d_status=status)
+        torch.cuda.synchronize()
+        assert int((status != 0).sum()) == 0, status.cpu().numpy()
+    return y.cpu().numpy()
+
+
+@pytest.mark.parametrize("engine", ENGINES)
+def test_c1_all_cells_60_calls(torch, engine):
+    from paper_2111_07436_amd import camp
+    wl = W.make_workload("c1")                       # 100 cells: one full wave + a ragged tail
+    m = camp.Mech(wl.mech)
+    log(f"c1 engine {engine}: {wl.n_cells} cells x {wl.n_calls} calls of {wl.dt} s")
+    y = gpu_solve(m, wl, engine)
+    sample = list(range(0, 100, 9)) + [99]
+    yr, st, _ = oracle_solve(wl.mech, wl.env, wl.y0, wl.dt, wl.n_calls, OR_RTOL, OR_ATOL, cells=sample)
+    assert np.all(st == 0)
+    assert_parity(y[sample], yr, what=f"c1/{engine}")
+
+
+@pytest.mark.parametrize("engine", ENGINES)
+def test_c3_multiphase_sample(torch, engine):
+    from paper_2111_07436_amd import camp
+    wl = W.make_workload("c3", n_cells=70)
+    m = camp.Mech(wl.mech)
+    log(f"c3 engine {engine}: {wl.n_cells} cells, dt {wl.dt}")
+    y = gpu_solve(m, wl, engine)
+    zero = np.all(wl.env.mass == 0.0, axis=1)
+    sample = [int(np.nonzero(zero)[0][0]), int(np.nonzero(~zero)[0][0]), int(np.nonzero(~zero)[0][1]), 69]
+    yr, st, _ = oracle_solve(wl.mech, wl.env, wl.y0, wl.dt, 1, OR_RTOL, OR_ATOL, cells=sample)
+    assert np.all(st == 0)
+    assert_parity(y[sample], yr, what=f"c3/{engine}")
+    # zero-aerosol cells keep zero condensed species
+    ng = wl.mech.n_gas
+    assert np.all(y[zero, ng:] == 0.0)
+
+
+def test_c2_full_size_sampled(torch):
+    """All 10,000 cells of the realistic gas config in the benchmark's launch configuration."""
+    from paper_2111_07436_amd import camp
+    wl = W.make_workload("c2")
+    m = camp.Mech(wl.mech)
+    log(f"c2 full: {wl.n_cells} cells, engine auto")
+    y = gpu_solve(m, wl, "auto")
+    sample = [0, 1, 4999, 9998, 9999]
+    yr, st, _ = oracle_solve(wl.mech, wl.env, wl.y0, wl.dt, 1, OR_RTOL, OR_ATOL, cells=sample)
+    assert np.all(st == 0)
+    assert_parity(y[sample], yr, what="c2/full")
+
+
+def test_engines_agree_and_tiling_invariant(torch):
+    from paper_2111_07436_amd import camp
+    wl = W.make_workload("c2", n_cells=300)
+    m = camp.Mech(wl.mech)
+    a = gpu_solve(m, wl, "wave", persistent=1, wg_per_cu=1)
+    b = gpu_solve(m, wl, "wave", persistent=0)
+    c = gpu_solve(m, wl, "wave", persistent=1, wg_per_cu=16)
+    assert np.array_equal(a, b) and np.array_equal(a, c)      # no cross-cell arithmetic
+    d = gpu_solve(m, wl, "lane")
+    e = gpu_solve(m, wl, "plain")
+    assert np.array_equal(d, e)                               # same phase functions
+    assert_parity(a, d, rel_tol=1e-4, what="wave vs lane")
+
+
+def test_closed_forms_on_gpu(torch):
+    from paper_2111_07436_amd import camp
+    import math
+    # emission + loss and A -> B -> C in one mechanism, several cells with different rates
+    sp = mechs.gas(["E", "A", "B", "C"])
+    rx = [W.Reaction(W.RXN_EMISSION, [], [0], [1.0], [4e-12, 0, 0, 0, 0, 0]),
+          W.Reaction(W.RXN_FIRST_ORDER_LOSS, [0], [], [], [7e-4, 0, 0, 0, 0, 0]),
+          W.Reaction(W.RXN_PHOTOLYSIS, [1], [2], [1.0], [2e-3, 1.0, 0, 0, 0, 0]),
+          W.Reaction(W.RXN_PHOTOLYSIS, [2], [3], [1.0], [5e-4, 0, 0, 0, 0, 0])]
+    mech = W.Mechanism(sp, [], rx)
+    n = 65
+    cz = np.linspace(-0.2, 1.0, n)
+    env = W.Environment(T=np.full(n, 290.0), P=np.full(n, 1e5), cos_sza=cz,
+                        radius=np.zeros((n, 0)), mass=np.zeros((n, 0)))
+    y0 = np.tile([3e-9, 1e-8, 3e-9, 0.0], (n, 1))
+    wl = W.Workload("closed", mech, env, y0, 3600.0, 1)
+    m = camp.Mech(mech)
+    for engine in ENGINES:
+        y = gpu_solve(m, wl, engine)
+        t = 3600.0
+        E, kl = 4e-12, 7e-4
+        k1 = 2e-3 * np.maximum(cz, 0.0)
+        k2 = 5e-4
+        yE = E / kl + (3e-9 - E / kl) * math.exp(-kl * t)
+        A = 1e-8 * np.exp(-k1 * t)
+        # B = B0 e^{-k2 t} + A0 k1 e^{-k2 t} (1 - e^{-(k1-k2) t}) / (k1 - k2), stable near k1 = k2
+        dk = k1 - k2
+        with np.errstate(divide="ignore", invalid="ignore"):
+            frac = np.where(dk == 0.0, t, -np.expm1(-dk * t) / dk)
+        B = 3e-9 * math.exp(-k2 * t) + 1e-8 * k1 * math.exp(-k2 * t) * frac
+        assert_parity(y[:, 0], np.full(n, yE), what=f"emission/{engine}")
+        assert_parity(y[:, 1], A, what=f"A/{engine}")
+        assert_parity(y[:, 2], B, what=f"B/{engine}")
+        assert np.allclose(y[:, 1:].sum(1), 1.3e-8, rtol=1e-12)
+
+
+def test_edge_cases(torch):
+    from paper_2111_07436_amd import camp
+    import torch as T
+    wl = W.make_workload("c1", n_cells=3)
+    m = camp.Mech(wl.mech)
+    denv = camp.DeviceEnv(wl.env)
+    # zero cells
+    y = T.zeros((0, m.n_state), dtype=T.float64, device="cuda")
+    st = T.zeros(0, dtype=T.int32, device="cuda")
+    m.solve_device(denv, y, 60.0, 1e-4, 1e-12, camp.make_opts("wave"), d_status=st)
+    # one cell, each engine, matches the 3-cell run's first row bitwise
+    for engine in ENGINES:
+        full = gpu_solve(m, wl, engine, calls=1)
+        one = gpu_solve(m, wl.take([0]), engine, calls=1)
+        assert np.array_equal(full[0], one[0]), engine
+    # invalid arguments
+    with pytest.raises(camp.CampError):
+        m.solve_device(denv, T.from_numpy(wl.y0.copy()).cuda(), -1.0, 1e-4, 1e-12)
+    with pytest.raises(camp.CampError):
+        m.solve_device(denv, T.from_numpy(wl.y0.copy()).cuda(), 60.0, 0.0, 1e-12)
+
+
+@pytest.mark.parametrize("engine", ENGINES)
+def test_failure_statuses(torch, engine):
+    from paper_2111_07436_amd import camp
+    import torch as T
+    wl = W.make_workload("c1", n_cells=4)
+    wl.env.T[2] = np.nan                                  # non-finite rate constants
+    m = camp.Mech(wl.mech)
+    denv = camp.DeviceEnv(wl.env)
+    y = T.from_numpy(wl.y0.copy()).cuda()
+    st = T.empty(4, dtype=T.int32, device="cuda")
+    m.solve_device(denv, y, 60.0, 1e-6, 1e-14, camp.make_opts(engine, max_steps=20000), d_status=st)
+    s = st.cpu().numpy()
+    out = y.cpu().numpy()
+    assert s[2] == 5 and s[0] == 0 and s[1] == 0 and s[3] == 0, s
+    assert np.array_equal(out[2], wl.y0[2])               # failed cell keeps its input
+    assert camp.count_failed(st) == 1
+    # max_steps = 1 -> status 1 everywhere; h_min larger than dt -> status 2
+    y = T.from_numpy(wl.y0.copy()).cuda()
+    m.solve_device(denv, y, 60.0, 1e-6, 1e-14, camp.make_opts(engine, max_steps=1), d_status=st)
+    s = st.cpu().numpy()
+    assert s[0] == 1 and s[1] == 1, s
+    y = T.from_numpy(wl.y0.copy()).cuda()
+    m.solve_device(denv, y, 60.0, 1e-6, 1e-14, camp.make_opts(engine, h_min=100.0), d_status=st)
+    s = st.cpu().numpy()
+    assert s[0] == 2 and s[1] == 2, s
+    assert np.array_equal(y.cpu().numpy()[0], wl.y0[0])
