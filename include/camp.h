@@ -186,7 +186,13 @@ typedef struct {
   int wg_per_cu;        /* FUSED_WAVE persistent grid: workgroups per CU, 0 = auto     */
   int persistent;       /* FUSED_*: 1 = persistent grid with a cell queue, 0 = one    */
                         /* workgroup per cell batch, -1 = auto                        */
-  int use_graph;        /* 1 = replay a captured hipGraph of the call's launches      */
+  int use_graph;        /* PLAIN: 1 = replay a captured hipGraph of each chunk of     */
+                        /* step-attempt launches                                      */
+  int waves_per_wg;     /* FUSED_WAVE: wavefronts (cells) per workgroup 1..8, 0 = auto */
+  int stage_tables;     /* FUSED_WAVE: 1 = index tables in LDS, 0 = global, -1 = auto  */
+  int full_newton;      /* 0 (default): Newton with Jacobian reuse; a cell that fails   */
+                        /* (status 1-4) is integrated again from its input with full    */
+                        /* Newton. 1: full Newton (fresh Jacobian and LU every iteration)*/
 } camp_opts;
 
 /* Per-cell counters (optional output). */

@@ -75,12 +75,7 @@ int upload(camp_mech* mh, int device, DeviceTables& out) {
          o_bwt = add(C.bwd_tasks.data(), sizeof(Task) * C.bwd_tasks.size()),
          o_lup = add(lup.data(), 4 * lup.size()), o_fwp = add(fwp.data(), 4 * fwp.size()),
          o_bwp = add(bwp.data(), 4 * bwp.size()),
-         o_wlu = add(mh->wlu.tasks.data(), sizeof(Task) * mh->wlu.tasks.size()),
-         o_wlulp = add(mh->wlu.level_pass.data(), 4 * mh->wlu.level_pass.size()),
-         o_wfw = add(mh->wfwd.tasks.data(), sizeof(Task) * mh->wfwd.tasks.size()),
-         o_wfwlp = add(mh->wfwd.level_pass.data(), 4 * mh->wfwd.level_pass.size()),
-         o_wbw = add(mh->wbwd.tasks.data(), sizeof(Task) * mh->wbwd.tasks.size()),
-         o_wbwlp = add(mh->wbwd.level_pass.data(), 4 * mh->wbwd.level_pass.size());
+         o_stage = add(mh->stage.bytes.data(), mh->stage.bytes.size());
 
   std::vector<char> host(total, 0);
   for (auto& it : items)
@@ -130,12 +125,20 @@ int upload(camp_mech* mh, int device, DeviceTables& out) {
   d.lu_pair = (const int2*)(b + o_lup);
   d.fwd_pair = (const int2*)(b + o_fwp);
   d.bwd_pair = (const int2*)(b + o_bwp);
-  d.wlu = (const DTask*)(b + o_wlu);
-  d.wlu_lp = (const int*)(b + o_wlulp);
-  d.wfwd = (const DTask*)(b + o_wfw);
-  d.wfwd_lp = (const int*)(b + o_wfwlp);
-  d.wbwd = (const DTask*)(b + o_wbw);
-  d.wbwd_lp = (const int*)(b + o_wbwlp);
+  const StageBlock& sb = mh->stage;
+  d.stage = sb.ok ? (const uint8_t*)(b + o_stage) : nullptr;
+  d.stage_bytes = sb.ok ? (int)sb.bytes.size() : 0;
+  d.so_rx = sb.off_rx;
+  d.so_col = sb.off_col;
+  d.so_rowptr = sb.off_rowptr;
+  d.so_diag = sb.off_diag;
+  d.so_fwd_rows = sb.off_fwd_rows;
+  d.so_fwd_lptr = sb.off_fwd_lptr;
+  d.so_bwd_rows = sb.off_bwd_rows;
+  d.so_bwd_lptr = sb.off_bwd_lptr;
+  d.so_lu_tk = sb.off_lu_tk;
+  d.so_lu_pr = sb.off_lu_pr;
+  d.so_lu_lptr = sb.off_lu_lptr;
   out.device = device;
   out.blob = blob;
   out.bytes = total;
@@ -188,6 +191,7 @@ SolveParams make_params(double dt, double rtol, double atol, const camp_opts* o)
   sp.h_min = (o && o->h_min > 0) ? o->h_min : 1e-14 * dt;
   sp.h_init = (o && o->h_init > 0) ? o->h_init : 0.0;
   sp.newton_tol = 0.1;
+  sp.full_newton = (o && o->full_newton) ? 1 : 0;
   return sp;
 }
 
@@ -229,40 +233,60 @@ int solve_device_tuned(camp_mech* mh, const DevMech& dm, int n_cells, double* d_
     const int slots = std::max(256, n_cus() * 4 * 64 * 2);
     e = run_fused_lane(dm, env, d_state, n_cells, sp, d_status, d_stats, slots, stream);
   } else {
-    if ((dm.N + kWave - 1) / kWave > 9) {
+    if ((dm.N + kWave - 1) / kWave > 9 || !dm.stage) {
       set_error("wavefront engine supports at most 576 state variables per cell");
       return CAMP_EINVAL;
     }
-    if (wave_lds_bytes(dm) > 160 * 1024) {
+    const int waves = std::max(1, tu.waves);
+    const bool stage = tu.stage != 0;
+    if (wave_wg_lds_bytes(dm, waves, stage) > kLdsBytes) {
       set_error("mechanism does not fit the wavefront engine's LDS budget");
       return CAMP_EINVAL;
     }
+    const int wg_total = (n_cells + waves - 1) / waves;
     if (tu.persistent) {
       int* queue = nullptr;
       e = hipMallocAsync((void**)&queue, 256, stream);
       if (e != hipSuccess) return hip_fail(e, "hipMallocAsync(queue)");
       e = launch_fill_int(queue, 1, 0, stream);
-      const int grid = std::min(n_cells, n_cus() * tu.grid_mult);
+      const int grid = std::max(1, std::min(wg_total, n_cus() * tu.grid_mult));
       if (e == hipSuccess)
-        e = launch_bdf_wave(dm, env, d_state, n_cells, sp, d_status, d_stats, queue, grid, stream);
+        e = launch_bdf_wave(dm, env, d_state, n_cells, sp, d_status, d_stats, queue, grid, waves,
+                            stage, stream);
       hipError_t e2 = hipFreeAsync(queue, stream);
       if (e == hipSuccess) e = e2;
     } else {
-      e = launch_bdf_wave(dm, env, d_state, n_cells, sp, d_status, d_stats, nullptr, n_cells, stream);
+      e = launch_bdf_wave(dm, env, d_state, n_cells, sp, d_status, d_stats, nullptr, wg_total,
+                          waves, stage, stream);
     }
   }
   if (e != hipSuccess) return hip_fail(e, "solve launch");
   return CAMP_OK;
 }
 
+// Occupancy-driven default: the largest number of wavefronts per workgroup (<= 8) such that
+// the workgroups resident on one CU hold the most cells, preferring staged tables.
 Tuning default_tuning(const DevMech& dm, int n_cells) {
   Tuning t;
-  const bool fits_wave = (dm.N + kWave - 1) / kWave <= 9 && wave_lds_bytes(dm) <= 160 * 1024;
+  const bool fits_wave = (dm.N + kWave - 1) / kWave <= 9 && dm.stage &&
+                         wave_wg_lds_bytes(dm, 1, false) <= kLdsBytes;
   t.engine = fits_wave ? CAMP_ENGINE_FUSED_WAVE : CAMP_ENGINE_FUSED_LANE;
   t.persistent = 1;
-  const size_t lds = wave_lds_bytes(dm);
-  int per_cu = (int)std::max<size_t>(1, (160 * 1024) / std::max<size_t>(lds, 1));
-  t.grid_mult = std::min(per_cu, 32);
+  int best_cells = 0;
+  const int wmax = wave_max_waves(dm.N);   // also the resident wavefronts per CU by VGPRs
+  for (int stage = 1; stage >= 0; --stage)
+    for (int w = 1; w <= wmax; ++w) {
+      const size_t b = wave_wg_lds_bytes(dm, w, stage != 0);
+      if (b > kLdsBytes) break;
+      const int wgs = (int)(kLdsBytes / b);
+      const int cells = std::min(wgs * w, wmax);
+      if (cells > best_cells || (cells == best_cells && stage && !t.stage)) {
+        best_cells = cells;
+        t.waves = w;
+        t.stage = stage;
+        t.grid_mult = std::max(1, std::min(wgs, wmax / w));
+      }
+    }
   (void)n_cells;
   return t;
 }
@@ -290,9 +314,7 @@ int camp_mech_load(const camp_reaction* rxns, int n_rxn, const camp_species* spe
       set_error(err);
       return CAMP_EINVAL;
     }
-    mh->wlu = build_wave_schedule(mh->C.lu_tasks, mh->C.lu_level_ptr, kWave);
-    mh->wfwd = build_wave_schedule(mh->C.fwd_tasks, mh->C.fwd_level_ptr, kWave);
-    mh->wbwd = build_wave_schedule(mh->C.bwd_tasks, mh->C.bwd_level_ptr, kWave);
+    mh->stage = build_stage_block(mh->C);
   } catch (const std::bad_alloc&) {
     delete mh;
     set_error("out of host memory");
@@ -366,8 +388,12 @@ int camp_solve_device(camp_mech* mh, int n_cells, double* d_state, const camp_en
     tu = default_tuning(*dm, n_cells);
     tu.engine = engine;
   }
-  if (opts && opts->persistent >= 0 && engine != CAMP_ENGINE_AUTO) tu.persistent = opts->persistent ? 1 : 0;
-  if (opts && opts->wg_per_cu > 0 && engine != CAMP_ENGINE_AUTO) tu.grid_mult = opts->wg_per_cu;
+  if (opts && engine != CAMP_ENGINE_AUTO) {
+    if (opts->persistent >= 0) tu.persistent = opts->persistent ? 1 : 0;
+    if (opts->wg_per_cu > 0) tu.grid_mult = opts->wg_per_cu;
+    if (opts->waves_per_wg > 0) tu.waves = std::min(opts->waves_per_wg, 8);
+    if (opts->stage_tables >= 0) tu.stage = opts->stage_tables ? 1 : 0;
+  }
   return solve_device_tuned(mh, *dm, n_cells, d_state, d_env, sp, opts, d_status, d_stats,
                             (hipStream_t)stream, tu);
 }
@@ -464,6 +490,10 @@ static int step_common(camp_mech* mh, int n_cells, int op, const double* kin, co
   const DevMech* dm = nullptr;
   int rc = resident(mh, &dm);
   if (rc != CAMP_OK) return rc;
+  if (!dm->stage || (dm->N + kWave - 1) / kWave > 9 || wave_cell_bytes(*dm) > kLdsBytes) {
+    set_error("single-step kernels support at most 576 state variables per cell");
+    return CAMP_EINVAL;
+  }
   hipError_t e = launch_wave_step(*dm, op, n_cells, kin, yin, out, gamma, (hipStream_t)stream);
   return e == hipSuccess ? CAMP_OK : hip_fail(e, "step kernel");
 }

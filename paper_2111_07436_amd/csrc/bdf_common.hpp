@@ -30,26 +30,13 @@ constexpr double kRestartFactor = 0.1;
 enum CellStatus : int { ST_OK = 0, ST_MAX_STEPS = 1, ST_H_MIN = 2, ST_ERR_FAIL = 3,
                         ST_NEWTON_FAIL = 4, ST_NONFINITE = 5 };
 
-// Matrix T = (R(rho) R(1))^T restricted to 0..q, R_{k,m}(rho) = prod_{i=1}^{k}(i-1-m rho)/i:
-// D_new[j] = sum_k T[j][k] D_old[k]. Row/col 0 is the identity.
-__device__ inline void rescale_matrix(int q, double rho, double T[kMaxOrder + 1][kMaxOrder + 1]) {
-  double Rr[kMaxOrder + 1][kMaxOrder + 1], Ru[kMaxOrder + 1][kMaxOrder + 1];
-  for (int m = 0; m <= q; ++m) {
-    Rr[0][m] = 1.0;
-    Ru[0][m] = 1.0;
-  }
-  for (int k = 1; k <= q; ++k)
-    for (int m = 0; m <= q; ++m) {
-      Rr[k][m] = Rr[k - 1][m] * ((k - 1) - m * rho) / k;
-      Ru[k][m] = Ru[k - 1][m] * (double)((k - 1) - m) / k;
-    }
-  // (Rr Ru)^T [j][k] = sum_m Rr[k][m] Ru[m][j]
-  for (int j = 0; j <= q; ++j)
-    for (int k = 0; k <= q; ++k) {
-      double s = 0.0;
-      for (int m = 0; m <= q; ++m) s += Rr[k][m] * Ru[m][j];
-      T[j][k] = s;
-    }
+// Changing the step from h to rho*h re-expresses the history as backward differences, at
+// the new spacing, of the polynomial P interpolating it. In Newton backward form
+// P(t_n - m rho h) = sum_k R_k(m) D[k] with R_k(m) = prod_{i=1}^{k} (i-1-m rho)/i, i.e. the
+// Horner form D0 + c_1(m)(D1 + c_2(m)(D2 + ...)) with c_k(m) = (k-1-m rho)/k. Evaluating P
+// at m = 0..q new steps back and differencing those values gives the new D[1..q].
+__device__ __forceinline__ double rescale_coef(int k, int m, double rho) {
+  return ((double)(k - 1) - m * rho) / k;
 }
 
 // Starting step (Hairer, Norsett & Wanner I, Sect. II.4) for order 1.

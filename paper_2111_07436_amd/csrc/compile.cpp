@@ -13,6 +13,7 @@
 #include <numeric>
 #include <set>
 #include <sstream>
+#include <cstring>
 
 #include "mech.hpp"
 
@@ -593,38 +594,78 @@ std::string compile_mechanism(const camp_reaction* rxns, int n_rxn, const camp_s
   return "";
 }
 
-WaveSchedule build_wave_schedule(const std::vector<Task>& tasks,
-                                 const std::vector<int>& level_ptr, int width) {
-  WaveSchedule ws;
-  ws.width = width;
-  const int L = (int)level_ptr.size() - 1;
-  ws.level_pass.assign(L + 1, 0);
-  int passes = 0;
-  for (int l = 0; l < L; ++l) {
-    std::vector<int> ids;
-    for (int q = level_ptr[l]; q < level_ptr[l + 1]; ++q) ids.push_back(q);
-    std::stable_sort(ids.begin(), ids.end(), [&](int a, int b) {
-      return (tasks[a].pend - tasks[a].pbeg) > (tasks[b].pend - tasks[b].pbeg);
-    });
-    std::vector<std::vector<int>> lane(width);
-    std::vector<long long> load(width, 0);
-    for (int id : ids) {
-      int best = 0;
-      for (int w = 1; w < width; ++w)
-        if (load[w] < load[best] || (load[w] == load[best] && lane[w].size() < lane[best].size()))
-          best = w;
-      lane[best].push_back(id);
-      load[best] += 1 + (tasks[id].pend - tasks[id].pbeg);
+StageBlock build_stage_block(const Compiled& C) {
+  StageBlock sb;
+  const int N = C.n_state, Z = C.nnz, R = C.n_rxn;
+  if (N >= 1023 || Z > 65535 || (long long)C.lu_pa.size() >= (1 << 20)) return sb;
+  std::vector<uint8_t>& b = sb.bytes;
+  auto put = [&](const void* src, size_t n) {
+    size_t off = (b.size() + 15) / 16 * 16;
+    b.resize(off + n);
+    if (n) std::memcpy(b.data() + off, src, n);
+    return (int)off;
+  };
+  // reactants packed 3 x 10 bits, 0x3FF = none
+  std::vector<uint32_t> rx(R);
+  for (int k = 0; k < R; ++k) {
+    uint32_t v = 0;
+    for (int o = 0; o < 3; ++o) {
+      int s = C.rx_react[3 * k + o];
+      v |= (uint32_t)(s < 0 ? 0x3FF : s) << (10 * o);
     }
-    size_t np = 0;
-    for (auto& v : lane) np = std::max(np, v.size());
-    for (size_t p = 0; p < np; ++p)
-      for (int w = 0; w < width; ++w)
-        ws.tasks.push_back(p < lane[w].size() ? tasks[lane[w][p]] : Task{-1, -1, 0, 0});
-    passes += (int)np;
-    ws.level_pass[l + 1] = passes;
+    rx[k] = v;
   }
-  return ws;
+  sb.off_rx = put(rx.data(), 4 * rx.size());
+  std::vector<uint16_t> col(C.col.begin(), C.col.end()), rp(C.row_ptr.begin(), C.row_ptr.end()),
+      dg(C.diag.begin(), C.diag.end());
+  sb.off_col = put(col.data(), 2 * col.size());
+  sb.off_rowptr = put(rp.data(), 2 * rp.size());
+  sb.off_diag = put(dg.data(), 2 * dg.size());
+  // solve rows per level, longest rows first inside a level
+  auto rows_by_level = [&](const std::vector<Task>& tasks, const std::vector<int>& lptr,
+                           std::vector<uint16_t>& rows, std::vector<uint16_t>& lp) {
+    lp.assign(lptr.size(), 0);
+    for (size_t l = 0; l + 1 < lptr.size(); ++l) {
+      std::vector<Task> t(tasks.begin() + lptr[l], tasks.begin() + lptr[l + 1]);
+      std::stable_sort(t.begin(), t.end(), [](const Task& a, const Task& c) {
+        return (a.pend - a.pbeg) > (c.pend - c.pbeg);
+      });
+      for (auto& x : t) rows.push_back((uint16_t)x.dst);
+      lp[l + 1] = (uint16_t)rows.size();
+    }
+  };
+  std::vector<uint16_t> fr, flp, br, blp;
+  rows_by_level(C.fwd_tasks, C.fwd_level_ptr, fr, flp);
+  rows_by_level(C.bwd_tasks, C.bwd_level_ptr, br, blp);
+  sb.off_fwd_rows = put(fr.data(), 2 * fr.size());
+  sb.off_fwd_lptr = put(flp.data(), 2 * flp.size());
+  sb.off_bwd_rows = put(br.data(), 2 * br.size());
+  sb.off_bwd_lptr = put(blp.data(), 2 * blp.size());
+  // LU tasks: x = dst | diag << 16 (0xFFFF: none), y = pbeg | count << 20; pairs pa | pb << 16
+  std::vector<uint32_t> tk, pr;
+  std::vector<uint32_t> llp(C.lu_level_ptr.size(), 0);
+  for (size_t l = 0; l + 1 < C.lu_level_ptr.size(); ++l) {
+    std::vector<Task> t(C.lu_tasks.begin() + C.lu_level_ptr[l], C.lu_tasks.begin() + C.lu_level_ptr[l + 1]);
+    std::stable_sort(t.begin(), t.end(), [](const Task& a, const Task& c) {
+      return (a.pend - a.pbeg) > (c.pend - c.pbeg);
+    });
+    for (auto& x : t) {
+      const int cnt = x.pend - x.pbeg;
+      if (cnt >= 4096) return StageBlock{};
+      tk.push_back((uint32_t)x.dst | ((uint32_t)(x.diag < 0 ? 0xFFFF : x.diag) << 16));
+      tk.push_back((uint32_t)pr.size() | ((uint32_t)cnt << 20));
+      for (int q = x.pbeg; q < x.pend; ++q)
+        pr.push_back((uint32_t)C.lu_pa[q] | ((uint32_t)C.lu_pb[q] << 16));
+    }
+    llp[l + 1] = (uint32_t)(tk.size() / 2);
+  }
+  sb.n_lu_tk = (int)(tk.size() / 2);
+  sb.off_lu_tk = put(tk.data(), 4 * tk.size());
+  sb.off_lu_pr = put(pr.data(), 4 * pr.size());
+  sb.off_lu_lptr = put(llp.data(), 4 * llp.size());
+  b.resize((b.size() + 15) / 16 * 16);
+  sb.ok = true;
+  return sb;
 }
 
 }  // namespace camp

@@ -47,10 +47,11 @@ struct DevMech {
   const int2* lu_pair;         // (pa, pb)
   const int2* fwd_pair;
   const int2* bwd_pair;
-  // wavefront schedules: per level, passes of 64 lane-tasks
-  const DTask* wlu;  const int* wlu_lp;
-  const DTask* wfwd; const int* wfwd_lp;
-  const DTask* wbwd; const int* wbwd_lp;
+  // compact latency-critical tables (one block, byte offsets; see StageBlock)
+  const uint8_t* stage;
+  int stage_bytes;
+  int so_rx, so_col, so_rowptr, so_diag, so_fwd_rows, so_fwd_lptr, so_bwd_rows, so_bwd_lptr;
+  int so_lu_tk, so_lu_pr, so_lu_lptr;
 };
 
 // Per-cell environment (device pointers, row-major [cells] / [cells][n_inst]).
@@ -66,6 +67,7 @@ struct DevEnv {
 struct SolveParams {
   double dt, rtol, atol, h_min, h_init, newton_tol;
   int max_order, max_steps, newton_maxit;
+  int full_newton;   // 1: full Newton from the start (no Jacobian reuse)
 };
 
 // BDF coefficients: gamma_q = sum_{j=1}^{q} 1/j; local error constant 1/(q+1).

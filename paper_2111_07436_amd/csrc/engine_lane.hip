@@ -16,7 +16,7 @@ namespace camp {
 struct LaneState {
   double *t, *h, *c_lu, *crate, *err, *dn_old;
   int *q, *n_equal, *attempts, *lu_valid, *lu_age, *consec_err, *consec_nf, *force_lu;
-  int *phase, *it, *fresh, *lu_ok, *cell;
+  int *phase, *it, *fresh, *lu_ok, *cell, *full;
   camp_cell_stats* st;
 };
 
@@ -145,21 +145,27 @@ struct Lane {
     }
   }
 
+  // Step change by rho (see rescale_coef): evaluate the interpolant at the new points, then
+  // difference.
   __device__ void rescale(int q, double rho) const {
-    double T[kMaxOrder + 1][kMaxOrder + 1];
-    rescale_matrix(kMaxOrder, rho, T);
     for (int i = 0; i < C.m.N; ++i) {
-      double old[kMaxOrder + 1];
+      double old[kMaxOrder + 1], a[kMaxOrder + 1];
 #pragma unroll
       for (int k = 0; k <= kMaxOrder; ++k) old[k] = k <= q ? D(k, i) : 0.0;
 #pragma unroll
-      for (int j = 1; j <= kMaxOrder; ++j)
-        if (j <= q) {
-          double s = 0.0;
+      for (int mm = 0; mm <= kMaxOrder; ++mm) {
+        double acc = 0.0;
 #pragma unroll
-          for (int k = 0; k <= kMaxOrder; ++k) s += T[j][k] * old[k];
-          D(j, i) = s;
-        }
+        for (int k = kMaxOrder; k >= 1; --k)
+          if (k <= q) acc = rescale_coef(k, mm, rho) * (old[k] + acc);
+        a[mm] = old[0] + acc;
+      }
+#pragma unroll
+      for (int lev = 1; lev <= kMaxOrder; ++lev) {
+#pragma unroll
+        for (int mm = 0; mm + lev <= kMaxOrder; ++mm) a[mm] -= a[mm + 1];
+        if (lev <= q) D(lev, i) = a[0];
+      }
     }
   }
 };
@@ -176,13 +182,16 @@ __device__ inline double lane_wrms_d_w(const Lane& L, double scale) {
 // ---------------------------------------------------------------- phase functions
 
 // Rate constants, initial state, starting step. Leaves the slot in PH_IDLE (ready to
-// predict) or PH_DONE (failed).
-__device__ void lane_init(const LaneCtx& C, int slot, int cell) {
+// predict) or PH_DONE (failed). full: integrate with full Newton (a retry keeps the
+// counters of the first attempt).
+__device__ void lane_init(const LaneCtx& C, int slot, int cell, int full) {
   const Lane L(C, slot);
   const DevMech& m = C.m;
   const LaneState& S = C.st;
   S.cell[slot] = cell;
+  S.full[slot] = full;
   camp_cell_stats cs = {0, 0, 0, 0, 0, 0, 0, 1};
+  if (full && !C.sp.full_newton) cs = S.st[slot];
   const double Tk = C.env.T[cell], Pp = C.env.P[cell];
   const double cz = C.env.cos_sza ? C.env.cos_sza[cell] : 1.0;
   const double* rad = C.env.radius ? C.env.radius + (size_t)cell * m.n_inst : nullptr;
@@ -308,7 +317,8 @@ __device__ void lane_predict(const LaneCtx& C, int slot, int new_step) {
     L.d(i) = 0.0;
   }
   const double c_lu = S.c_lu[slot];
-  const int need = S.force_lu[slot] || !S.lu_valid[slot] || fabs(c / c_lu - 1.0) > kLuGammaDrift ||
+  const int need = S.full[slot] || S.force_lu[slot] || !S.lu_valid[slot] ||
+                   fabs(c / c_lu - 1.0) > kLuGammaDrift ||
                    S.lu_age[slot] >= kLuMaxAge;
   S.fresh[slot] = need;
   S.lu_ok[slot] = 1;
@@ -340,6 +350,23 @@ __device__ void lane_newton(const LaneCtx& C, int slot) {
   const LaneState& S = C.st;
   const int it = S.it[slot];
   const double c = S.h[slot] / bdf_gamma(S.q[slot]);
+  if (S.full[slot] && it > 0) {
+    // full Newton: Jacobian and LU at the current iterate
+    L.newton_matrix(c);
+    const int lok = L.lu();
+    S.st[slot].n_jac++;
+    S.st[slot].n_lu++;
+    S.lu_valid[slot] = lok;
+    S.lu_ok[slot] = lok;
+    S.c_lu[slot] = c;
+    S.lu_age[slot] = 0;
+    S.crate[slot] = 1.0;
+    S.fresh[slot] = 1;
+    if (!lok) {
+      S.phase[slot] = PH_FINISH;
+      return;
+    }
+  }
   const double c_lu = S.c_lu[slot];
   const double scale = (c == c_lu) ? 1.0 : 2.0 / (1.0 + c / c_lu);
   const int ok = L.forcing();
@@ -508,11 +535,18 @@ __device__ inline void lane_store_stats(const LaneCtx& C, int slot) {
 // ------------------------------------------------------------------ plain engine kernels
 // slot == cell. `active_count` accumulates the cells still integrating.
 
-__global__ __launch_bounds__(256) void plain_init_kernel(LaneCtx C) {
+__device__ inline bool retry_status(int s) { return s >= ST_MAX_STEPS && s <= ST_NEWTON_FAIL; }
+
+// retry == 0: start every cell; retry == 1: restart with full Newton only the cells whose
+// first integration failed (the others stay done).
+__global__ __launch_bounds__(256) void plain_init_kernel(LaneCtx C, int retry) {
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= C.n_cells) return;
+  if (retry) {
+    if (!retry_status(C.status[c])) return;
+  }
   C.status[c] = -1;
-  lane_init(C, c, c);
+  lane_init(C, c, c, retry ? 1 : C.sp.full_newton);
   C.st.it[c] = 1;   // "new step" flag for the first predict
 }
 
@@ -565,16 +599,19 @@ __global__ __launch_bounds__(256) void fused_lane_kernel(LaneCtx C, int n_slots,
   while (true) {
     const int cell = atomicAdd(queue, 1);
     if (cell >= C.n_cells) break;
-    C.status[cell] = -1;
-    lane_init(C, slot, cell);
-    int new_step = 1;
-    while (C.st.phase[slot] != PH_DONE) {
-      lane_predict(C, slot, new_step);
-      if (C.st.phase[slot] != PH_NEWTON) break;
-      lane_lu(C, slot);
-      while (C.st.phase[slot] == PH_NEWTON) lane_newton(C, slot);
-      if (C.st.phase[slot] == PH_DONE) break;
-      lane_finish(C, slot, &new_step);
+    for (int full = C.sp.full_newton; full < 2; ++full) {
+      C.status[cell] = -1;
+      lane_init(C, slot, cell, full);
+      int new_step = 1;
+      while (C.st.phase[slot] != PH_DONE) {
+        lane_predict(C, slot, new_step);
+        if (C.st.phase[slot] != PH_NEWTON) break;
+        lane_lu(C, slot);
+        while (C.st.phase[slot] == PH_NEWTON) lane_newton(C, slot);
+        if (C.st.phase[slot] == PH_DONE) break;
+        lane_finish(C, slot, &new_step);
+      }
+      if (!retry_status(C.status[cell])) break;
     }
     lane_store_stats(C, slot);
   }
@@ -608,7 +645,7 @@ inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 struct LaneLayout {
   size_t bytes = 0;
   size_t off_kc, off_P, off_M, off_y, off_x, off_D, off_d, off_psi, off_w, off_f;
-  size_t off_dbl[6], off_int[13], off_stats, off_counter;
+  size_t off_dbl[6], off_int[14], off_stats, off_counter;
   LaneLayout(const DevMech& m, size_t slots) {
     const size_t np = (size_t)(m.n_part > m.R ? m.n_part : m.R);
     size_t o = 0;
@@ -647,9 +684,10 @@ void bind(LaneCtx& C, char* base, const LaneLayout& L) {
   S.crate = D(L.off_dbl[3]);
   S.err = D(L.off_dbl[4]);
   S.dn_old = D(L.off_dbl[5]);
-  int** ints[13] = {&S.q, &S.n_equal, &S.attempts, &S.lu_valid, &S.lu_age, &S.consec_err,
-                    &S.consec_nf, &S.force_lu, &S.phase, &S.it, &S.fresh, &S.lu_ok, &S.cell};
-  for (int i = 0; i < 13; ++i) *ints[i] = I(L.off_int[i]);
+  int** ints[14] = {&S.q,     &S.n_equal, &S.attempts, &S.lu_valid, &S.lu_age,
+                    &S.consec_err, &S.consec_nf, &S.force_lu, &S.phase, &S.it,
+                    &S.fresh, &S.lu_ok, &S.cell, &S.full};
+  for (int i = 0; i < 14; ++i) *ints[i] = I(L.off_int[i]);
   S.st = reinterpret_cast<camp_cell_stats*>(base + L.off_stats);
 }
 
@@ -697,7 +735,6 @@ hipError_t run_plain(const DevMech& m, const DevEnv& env, double* state, int n_c
   int* counter = reinterpret_cast<int*>(base + lay.off_counter);
   int* host_counter = g_pinned_counter();
   const dim3 grid((n_cells + 255) / 256), block(256);
-  hipLaunchKernelGGL(plain_init_kernel, grid, block, 0, stream, C);
   constexpr int kChunk = 4;
   auto enqueue_chunk = [&]() {
     for (int a = 0; a < kChunk; ++a) {
@@ -724,25 +761,30 @@ hipError_t run_plain(const DevMech& m, const DevEnv& env, double* state, int n_c
       return e;
     }
   }
-  // Each chunk runs kChunk step attempts for every active cell; stop when none is active.
+  // Pass 0 integrates every cell; pass 1 restarts with full Newton the cells whose first
+  // integration failed. Each chunk runs kChunk step attempts for every active cell; a pass
+  // stops when no cell is active.
   const long long max_chunks = (long long)sp.max_steps / kChunk + 2;
-  for (long long ch = 0; ch < max_chunks; ++ch) {
-    if (exec) {
-      e = hipGraphLaunch(exec, stream);
-    } else {
-      enqueue_chunk();
-      e = hipGetLastError();
-    }
-    if (e != hipSuccess) break;
-    if (host_counter) {
-      e = hipMemcpyAsync(host_counter, counter, sizeof(int), hipMemcpyDeviceToHost, stream);
-      if (e == hipSuccess) e = hipStreamSynchronize(stream);
+  for (int pass = sp.full_newton ? 1 : 0; pass < 2 && e == hipSuccess; ++pass) {
+    hipLaunchKernelGGL(plain_init_kernel, grid, block, 0, stream, C, pass);
+    for (long long ch = 0; ch < max_chunks; ++ch) {
+      if (exec) {
+        e = hipGraphLaunch(exec, stream);
+      } else {
+        enqueue_chunk();
+        e = hipGetLastError();
+      }
       if (e != hipSuccess) break;
-      if (*host_counter == 0) break;
-    } else {
-      int hc = 0;
-      e = hipMemcpy(&hc, counter, sizeof(int), hipMemcpyDeviceToHost);
-      if (e != hipSuccess || hc == 0) break;
+      if (host_counter) {
+        e = hipMemcpyAsync(host_counter, counter, sizeof(int), hipMemcpyDeviceToHost, stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(stream);
+        if (e != hipSuccess) break;
+        if (*host_counter == 0) break;
+      } else {
+        int hc = 0;
+        e = hipMemcpy(&hc, counter, sizeof(int), hipMemcpyDeviceToHost);
+        if (e != hipSuccess || hc == 0) break;
+      }
     }
   }
   if (e == hipSuccess) {

@@ -6,9 +6,13 @@
 // state, right-hand side, rates and partial derivatives live in LDS, and its BDF history
 // lives in registers with species t held by lane t % 64. Sparse work is spread over the
 // 64 lanes by the level-scheduled tables built on the host: every task of one dependency
-// level runs in parallel, levels are separated by a workgroup barrier. Control decisions
-// use wavefront reductions, so they are uniform and need no masking. When a cell is done
-// the wavefront takes the next one from a device-side queue (or from the grid index).
+// level runs in parallel, levels are separated by a wavefront-scoped barrier. Control
+// decisions use wavefront reductions, so they are uniform and need no masking.
+//
+// A workgroup holds several wavefronts (cells) that share one LDS copy of the
+// latency-critical index tables (reactants, CSR pattern with level-ordered solve rows,
+// Crout LU tasks and pairs), staged once per workgroup. When a cell is done the wavefront
+// takes the next one from a device-side queue (persistent grid) or from the grid index.
 //
 // Forcing and Jacobian (paper Sect. 2.4.2): f_i = sum_k S_ik r_k and
 // J_ij = sum_k S_ik dr_k/dy_j, with r_k = k_k prod y over reactant occurrences.
@@ -19,9 +23,36 @@ namespace camp {
 
 namespace {
 
+// Orders LDS traffic of one wavefront: LDS instructions of a wavefront execute in order,
+// so a release/acquire fence at wavefront scope is all that lanes need to see each
+// other's writes.
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Accessors of the compact table block, in LDS (staged) or in global memory.
+struct Tabs {
+  const char* b;
+  const DevMech& m;
+  __device__ uint32_t rx(int k) const { return reinterpret_cast<const uint32_t*>(b + m.so_rx)[k]; }
+  __device__ int col(int q) const { return reinterpret_cast<const uint16_t*>(b + m.so_col)[q]; }
+  __device__ int rowptr(int t) const { return reinterpret_cast<const uint16_t*>(b + m.so_rowptr)[t]; }
+  __device__ int dg(int t) const { return reinterpret_cast<const uint16_t*>(b + m.so_diag)[t]; }
+  __device__ int fwd_row(int i) const { return reinterpret_cast<const uint16_t*>(b + m.so_fwd_rows)[i]; }
+  __device__ int fwd_lp(int l) const { return reinterpret_cast<const uint16_t*>(b + m.so_fwd_lptr)[l]; }
+  __device__ int bwd_row(int i) const { return reinterpret_cast<const uint16_t*>(b + m.so_bwd_rows)[i]; }
+  __device__ int bwd_lp(int l) const { return reinterpret_cast<const uint16_t*>(b + m.so_bwd_lptr)[l]; }
+  __device__ uint2 lu_tk(int i) const { return reinterpret_cast<const uint2*>(b + m.so_lu_tk)[i]; }
+  __device__ uint32_t lu_pr(int q) const { return reinterpret_cast<const uint32_t*>(b + m.so_lu_pr)[q]; }
+  __device__ int lu_lp(int l) const { return (int)reinterpret_cast<const uint32_t*>(b + m.so_lu_lptr)[l]; }
+};
+
 template <int NPL>
 struct WaveCell {
   const DevMech& m;
+  Tabs tb;
   double* M;
   double* yl;
   double* xl;
@@ -43,68 +74,75 @@ struct WaveCell {
   // P[k] = r_k from yl; then f for owned species. yl must be visible to all lanes.
   __device__ void forcing(double (&f)[NPL]) const {
     for (int k = lane; k < m.R; k += kWave) {
-      const int* rr = m.rx_react + 3 * k;
+      const uint32_t v = tb.rx(k);
+      const int a = v & 0x3FF, b = (v >> 10) & 0x3FF, c = (v >> 20) & 0x3FF;
       double r = kc[k];
-      int a = rr[0], b = rr[1], c = rr[2];
-      if (a >= 0) r *= yl[a];
-      if (b >= 0) r *= yl[b];
-      if (c >= 0) r *= yl[c];
+      if (a != 0x3FF) r *= yl[a];
+      if (b != 0x3FF) r *= yl[b];
+      if (c != 0x3FF) r *= yl[c];
       P[k] = r;
     }
-    __syncthreads();
+    wave_sync();
 #pragma unroll
     for (int i = 0; i < NPL; ++i) {
       const int t = lane + kWave * i;
       double acc = 0.0;
-      if (t < m.N)
-        for (int q = m.term_ptr[t]; q < m.term_ptr[t + 1]; ++q) acc += m.term_coef[q] * P[m.term_rxn[q]];
+      if (t < m.N) {
+        const int q0 = m.term_ptr[t], q1 = m.term_ptr[t + 1];
+#pragma unroll 4
+        for (int q = q0; q < q1; ++q) acc += m.term_coef[q] * P[m.term_rxn[q]];
+      }
       f[i] = acc;
     }
-    __syncthreads();
+    wave_sync();
   }
 
   // M = I - c J(yl) in the filled pattern (fill slots 0 off the diagonal).
   __device__ void newton_matrix(double c) const {
     for (int k = lane; k < m.R; k += kWave) {
-      const int* rr = m.rx_react + 3 * k;
-      const int a = rr[0], b = rr[1], cc = rr[2];
+      const uint32_t v = tb.rx(k);
+      const int a = v & 0x3FF, b = (v >> 10) & 0x3FF, cc = (v >> 20) & 0x3FF;
       const double kk = kc[k];
       const int base = m.rx_pofs[k];
-      const double ya = a >= 0 ? yl[a] : 1.0, yb = b >= 0 ? yl[b] : 1.0, yc = cc >= 0 ? yl[cc] : 1.0;
-      if (a >= 0) P[base] = kk * yb * yc;
-      if (b >= 0) P[base + 1] = kk * ya * yc;
-      if (cc >= 0) P[base + 2] = kk * ya * yb;
+      const double ya = a != 0x3FF ? yl[a] : 1.0, yb = b != 0x3FF ? yl[b] : 1.0,
+                   yc = cc != 0x3FF ? yl[cc] : 1.0;
+      if (a != 0x3FF) P[base] = kk * yb * yc;
+      if (b != 0x3FF) P[base + 1] = kk * ya * yc;
+      if (cc != 0x3FF) P[base + 2] = kk * ya * yb;
     }
-    __syncthreads();
+    wave_sync();
     for (int s = lane; s < m.Z; s += kWave) {
       double acc = 0.0;
-      for (int q = m.jc_ptr[s]; q < m.jc_ptr[s + 1]; ++q) acc += m.jc_coef[q] * P[m.jc_part[q]];
+      const int q0 = m.jc_ptr[s], q1 = m.jc_ptr[s + 1];
+#pragma unroll 4
+      for (int q = q0; q < q1; ++q) acc += m.jc_coef[q] * P[m.jc_part[q]];
       M[s] = (m.is_diag[s] ? 1.0 : 0.0) - c * acc;
     }
-    __syncthreads();
+    wave_sync();
   }
 
-  // In-place LU of M, one dependency level at a time. Returns 0 if a pivot is not a
+  // In-place Crout LU of M, one dependency level at a time. Returns 0 if a pivot is not a
   // finite nonzero.
   __device__ int lu() const {
     for (int l = 0; l < m.lu_levels; ++l) {
-      for (int p = m.wlu_lp[l]; p < m.wlu_lp[l + 1]; ++p) {
-        const DTask t = m.wlu[p * kWave + lane];
-        if (t.dst >= 0) {
-          double acc = M[t.dst];
-          for (int q = t.pbeg; q < t.pend; ++q) {
-            const int2 pr = m.lu_pair[q];
-            acc -= M[pr.x] * M[pr.y];
-          }
-          if (t.diag >= 0) acc /= M[t.diag];
-          M[t.dst] = acc;
+      const int lo = tb.lu_lp(l), hi = tb.lu_lp(l + 1);
+      for (int i = lo + lane; i < hi; i += kWave) {
+        const uint2 t = tb.lu_tk(i);
+        const int dst = t.x & 0xFFFF, dgs = t.x >> 16;
+        const int pb = t.y & 0xFFFFF, cnt = t.y >> 20;
+        double acc = M[dst];
+        for (int q = 0; q < cnt; ++q) {
+          const uint32_t pr = tb.lu_pr(pb + q);
+          acc -= M[pr & 0xFFFF] * M[pr >> 16];
         }
+        if (dgs != 0xFFFF) acc /= M[dgs];
+        M[dst] = acc;
       }
-      __syncthreads();
+      wave_sync();
     }
     int bad = 0;
     for (int t = lane; t < m.N; t += kWave) {
-      const double u = M[m.diag[t]];
+      const double u = M[tb.dg(t)];
       if (!(fabs(u) > 0.0) || !isfinite(u)) bad = 1;
     }
     return !wave_or(bad);
@@ -115,86 +153,70 @@ struct WaveCell {
     return lu();
   }
 
-  // xl <- (LU)^-1 xl
+  // xl <- (LU)^-1 xl: forward then backward substitution over the CSR rows, level by level.
   __device__ void solve() const {
     for (int l = 0; l < m.fwd_levels; ++l) {
-      for (int p = m.wfwd_lp[l]; p < m.wfwd_lp[l + 1]; ++p) {
-        const DTask t = m.wfwd[p * kWave + lane];
-        if (t.dst >= 0) {
-          double acc = xl[t.dst];
-          for (int q = t.pbeg; q < t.pend; ++q) {
-            const int2 pr = m.fwd_pair[q];
-            acc -= M[pr.x] * xl[pr.y];
-          }
-          xl[t.dst] = acc;
-        }
+      const int lo = tb.fwd_lp(l), hi = tb.fwd_lp(l + 1);
+      for (int i = lo + lane; i < hi; i += kWave) {
+        const int t = tb.fwd_row(i);
+        double acc = xl[t];
+        const int q1 = tb.dg(t);
+        for (int q = tb.rowptr(t); q < q1; ++q) acc -= M[q] * xl[tb.col(q)];
+        xl[t] = acc;
       }
-      __syncthreads();
+      wave_sync();
     }
     for (int l = 0; l < m.bwd_levels; ++l) {
-      for (int p = m.wbwd_lp[l]; p < m.wbwd_lp[l + 1]; ++p) {
-        const DTask t = m.wbwd[p * kWave + lane];
-        if (t.dst >= 0) {
-          double acc = xl[t.dst];
-          for (int q = t.pbeg; q < t.pend; ++q) {
-            const int2 pr = m.bwd_pair[q];
-            acc -= M[pr.x] * xl[pr.y];
-          }
-          xl[t.dst] = acc / M[t.diag];
-        }
+      const int lo = tb.bwd_lp(l), hi = tb.bwd_lp(l + 1);
+      for (int i = lo + lane; i < hi; i += kWave) {
+        const int t = tb.bwd_row(i);
+        double acc = xl[t];
+        const int d = tb.dg(t), q1 = tb.rowptr(t + 1);
+        for (int q = d + 1; q < q1; ++q) acc -= M[q] * xl[tb.col(q)];
+        xl[t] = acc / M[d];
       }
-      __syncthreads();
+      wave_sync();
     }
   }
 };
 
-// D[j] <- sum_k T[j][k] D[k] for j, k <= q (T from rescale_matrix, q-independent block).
+// Step change by rho: D[1..q] become the backward differences at the new spacing of the
+// polynomial interpolating the history (rescale_point / rescale_differences).
 template <int NPL>
 __device__ __forceinline__ void rescale_hist(double (&D)[kHist][NPL], int q, double rho) {
-  double T[kMaxOrder + 1][kMaxOrder + 1];
-  rescale_matrix(kMaxOrder, rho, T);
 #pragma unroll
   for (int i = 0; i < NPL; ++i) {
-    double nd[kMaxOrder + 1];
+    double a[kMaxOrder + 1];
 #pragma unroll
-    for (int j = 0; j <= kMaxOrder; ++j) {
-      double s = 0.0;
+    for (int mm = 0; mm <= kMaxOrder; ++mm) {
+      double acc = 0.0;
 #pragma unroll
-      for (int k = 0; k <= kMaxOrder; ++k)
-        if (k <= q) s += T[j][k] * D[k][i];
-      nd[j] = s;
+      for (int k = kMaxOrder; k >= 1; --k)
+        if (k <= q) acc = rescale_coef(k, mm, rho) * (D[k][i] + acc);
+      a[mm] = D[0][i] + acc;
     }
 #pragma unroll
-    for (int j = 1; j <= kMaxOrder; ++j)
-      if (j <= q) D[j][i] = nd[j];
+    for (int lev = 1; lev <= kMaxOrder; ++lev) {
+#pragma unroll
+      for (int mm = 0; mm + lev <= kMaxOrder; ++mm) a[mm] -= a[mm + 1];
+      if (lev <= q) D[lev][i] = a[0];
+    }
   }
 }
 
+// Integrates one cell over the host step from its input row (rate constants already in
+// LDS; `bad` flags a non-finite rate constant on this lane). full != 0: full Newton, with a
+// fresh Jacobian and LU at every iteration; else Newton with Jacobian reuse. On success
+// the state row is overwritten; on failure it is left as it was.
 template <int NPL>
-__device__ void solve_one_cell(const DevMech& m, const DevEnv& env, double* state, int cell,
-                               const SolveParams& sp, int* status_out, camp_cell_stats* stats_out,
-                               WaveCell<NPL>& W) {
+__device__ __forceinline__ int integrate(const DevMech& m, double* yrow, const SolveParams& sp, int bad, int full,
+                         camp_cell_stats& cs, const WaveCell<NPL>& W) {
   const int lane = W.lane;
   const int N = m.N;
-  camp_cell_stats cs = {0, 0, 0, 0, 0, 0, 0, 0};
   int status = ST_OK;
-
-  // ---- rate constants (fixed over the host step) ----
-  const double Tk = env.T[cell], Pp = env.P[cell];
-  const double cz = env.cos_sza ? env.cos_sza[cell] : 1.0;
-  const double* rad = env.radius ? env.radius + (size_t)cell * m.n_inst : nullptr;
-  const double* mas = env.mass ? env.mass + (size_t)cell * m.n_inst : nullptr;
-  const double* ovr = env.override_ ? env.override_ + (size_t)cell * m.n_ext : nullptr;
-  int bad = 0;
-  for (int k = lane; k < m.R; k += kWave) {
-    const double v = rate_constant(m, k, Tk, Pp, cz, rad, mas, ovr);
-    W.kc[k] = v;
-    if (!isfinite(v)) bad = 1;
-  }
 
   // ---- initial state ----
   double D[kHist][NPL];
-  double* yrow = state + (size_t)cell * N;
 #pragma unroll
   for (int i = 0; i < NPL; ++i) {
     const int t = lane + kWave * i;
@@ -207,10 +229,8 @@ __device__ void solve_one_cell(const DevMech& m, const DevEnv& env, double* stat
 #pragma unroll
     for (int j = 1; j < kHist; ++j) D[j][i] = 0.0;
   }
-  __syncthreads();
-  if (wave_or(bad)) {
-    status = ST_NONFINITE;
-  }
+  wave_sync();
+  if (wave_or(bad)) status = ST_NONFINITE;
 
   const double span = sp.dt;
   double w[NPL], f0[NPL], d[NPL];
@@ -236,7 +256,7 @@ __device__ void solve_one_cell(const DevMech& m, const DevEnv& env, double* stat
       const int t = lane + kWave * i;
       if (t < N) W.yl[t] = D[0][i] + h0 * f0[i];
     }
-    __syncthreads();
+    wave_sync();
     double f1[NPL];
     W.forcing(f1);
     cs.n_f++;
@@ -274,9 +294,9 @@ __device__ void solve_one_cell(const DevMech& m, const DevEnv& env, double* stat
     while (true) {
       if (++attempts > sp.max_steps) { status = ST_MAX_STEPS; break; }
       if (h < sp.h_min) { status = ST_H_MIN; break; }
-      double gq = bdf_gamma(q);
+      const double gq = bdf_gamma(q);
       const double c = h / gq;
-      double yp[NPL], psi[NPL], yv[NPL];
+      double psi[NPL], yv[NPL];
 #pragma unroll
       for (int i = 0; i < NPL; ++i) {
         double s = D[0][i], ps = 0.0, g = 0.0;
@@ -288,14 +308,13 @@ __device__ void solve_one_cell(const DevMech& m, const DevEnv& env, double* stat
             ps += g * D[j][i];
           }
         }
-        yp[i] = s;
         psi[i] = ps / gq;
         yv[i] = s;
         d[i] = 0.0;
         const int tt = lane + kWave * i;
         if (tt < N) W.yl[tt] = s;
       }
-      __syncthreads();
+      wave_sync();
       int fresh = 0, lu_ok = 1;
       if (force_lu || !lu_valid || fabs(c / c_lu - 1.0) > kLuGammaDrift || lu_age >= kLuMaxAge) {
         lu_ok = W.newton_matrix_lu(c);
@@ -310,7 +329,6 @@ __device__ void solve_one_cell(const DevMech& m, const DevEnv& env, double* stat
       bool conv = false;
       int nonfin = 0;
       if (lu_ok) {
-        const double scale = (c == c_lu) ? 1.0 : 2.0 / (1.0 + c / c_lu);
         double dn_old = 0.0;
         for (int it = 0; it < sp.newton_maxit; ++it) {
           if (it > 0) {
@@ -319,8 +337,20 @@ __device__ void solve_one_cell(const DevMech& m, const DevEnv& env, double* stat
               const int tt = lane + kWave * i;
               if (tt < N) W.yl[tt] = yv[i];
             }
-            __syncthreads();
+            wave_sync();
           }
+          if (full && (it > 0 || !fresh)) {
+            lu_ok = W.newton_matrix_lu(c);   // Jacobian at the current iterate
+            cs.n_jac++;
+            cs.n_lu++;
+            lu_valid = lu_ok;
+            c_lu = c;
+            lu_age = 0;
+            crate = 1.0;
+            fresh = 1;
+            if (!lu_ok) break;
+          }
+          const double scale = (c == c_lu) ? 1.0 : 2.0 / (1.0 + c / c_lu);
           double f[NPL];
           W.forcing(f);
           cs.n_f++;
@@ -334,7 +364,7 @@ __device__ void solve_one_cell(const DevMech& m, const DevEnv& env, double* stat
             }
           }
           if (wave_or(nf)) { nonfin = 1; break; }
-          __syncthreads();
+          wave_sync();
           W.solve();
           double dl[NPL];
 #pragma unroll
@@ -342,7 +372,7 @@ __device__ void solve_one_cell(const DevMech& m, const DevEnv& env, double* stat
             const int tt = lane + kWave * i;
             dl[i] = tt < N ? W.xl[tt] * scale : 0.0;
           }
-          __syncthreads();
+          wave_sync();
           const double dn = W.wrms(dl, w);
           cs.newton_iters++;
 #pragma unroll
@@ -385,7 +415,7 @@ __device__ void solve_one_cell(const DevMech& m, const DevEnv& env, double* stat
             const int tt = lane + kWave * i;
             if (tt < N) W.yl[tt] = D[0][i];
           }
-          __syncthreads();
+          wave_sync();
           double fn[NPL];
           W.forcing(fn);
           cs.n_f++;
@@ -464,42 +494,147 @@ __device__ void solve_one_cell(const DevMech& m, const DevEnv& env, double* stat
     }
   }
   cs.order = q;
+  return status;
+}
+
+// Rate constants, then the integration; a cell whose Newton-with-reuse integration fails
+// (too many steps, step below the minimum, repeated error-test or Newton failures) is
+// integrated again from its input with full Newton.
+template <int NPL>
+__device__ void solve_one_cell(const DevMech& m, const DevEnv& env, double* state, int cell,
+                               const SolveParams& sp, int* status_out, camp_cell_stats* stats_out,
+                               const WaveCell<NPL>& W) {
+  const int lane = W.lane;
+  camp_cell_stats cs = {0, 0, 0, 0, 0, 0, 0, 0};
+  const double Tk = env.T[cell], Pp = env.P[cell];
+  const double cz = env.cos_sza ? env.cos_sza[cell] : 1.0;
+  const double* rad = env.radius ? env.radius + (size_t)cell * m.n_inst : nullptr;
+  const double* mas = env.mass ? env.mass + (size_t)cell * m.n_inst : nullptr;
+  const double* ovr = env.override_ ? env.override_ + (size_t)cell * m.n_ext : nullptr;
+  int bad = 0;
+  for (int k = lane; k < m.R; k += kWave) {
+    const double v = rate_constant(m, k, Tk, Pp, cz, rad, mas, ovr);
+    W.kc[k] = v;
+    if (!isfinite(v)) bad = 1;
+  }
+  double* yrow = state + (size_t)cell * m.N;
+  int status = ST_OK;
+  for (int full = sp.full_newton ? 1 : 0; full < 2; ++full) {
+    status = integrate<NPL>(m, yrow, sp, bad, full, cs, W);
+    if (status < ST_MAX_STEPS || status > ST_NEWTON_FAIL) break;
+  }
   if (lane == 0) {
     status_out[cell] = status;
     if (stats_out) stats_out[cell] = cs;
   }
+  wave_sync();
+}
+
+__device__ inline size_t cell_doubles(const DevMech& m) {
+  const int np = m.n_part > m.R ? m.n_part : m.R;
+  return (size_t)m.Z + 2 * (size_t)m.N + np + m.R;
+}
+
+// Copies the compact table block into LDS (16-byte units) and returns its base.
+template <bool kStage>
+__device__ __forceinline__ const char* stage_tables(const DevMech& m, double* lds) {
+  if (!kStage) return reinterpret_cast<const char*>(m.stage);
+  const uint4* src = reinterpret_cast<const uint4*>(m.stage);
+  uint4* dst = reinterpret_cast<uint4*>(lds);
+  for (int i = threadIdx.x; i < m.stage_bytes / 16; i += blockDim.x) dst[i] = src[i];
   __syncthreads();
+  return reinterpret_cast<const char*>(lds);
 }
 
 }  // namespace
 
-// One wavefront per workgroup. queue != nullptr: persistent grid pulling cells from the
-// counter; else cell = blockIdx.x.
+constexpr int kMaxWavesPerWG = 8;
+// Up to 3 species per lane the kernel fits 256 VGPRs (two wavefronts per SIMD, workgroups
+// of up to 8 wavefronts); larger states get 512 VGPRs (workgroups of up to 4 wavefronts).
 template <int NPL>
-__global__ __launch_bounds__(kWave) void bdf_wave_kernel(DevMech m, DevEnv env, double* state,
-                                                        int n_cells, SolveParams sp, int* status,
-                                                        camp_cell_stats* stats, int* queue) {
+constexpr int max_waves_per_wg() { return NPL <= 3 ? 8 : 4; }
+int wave_max_waves(int n_state) { return (n_state + kWave - 1) / kWave <= 3 ? 8 : 4; }
+
+// blockDim.x = 64 * W: W wavefronts, one cell each. queue != nullptr: persistent grid
+// pulling cells from the counter; else cell = blockIdx.x * W + wavefront.
+template <int NPL, bool kStage>
+__global__ __launch_bounds__(kWave * max_waves_per_wg<NPL>()) void bdf_wave_kernel(
+    DevMech m, DevEnv env, double* state, int n_cells, SolveParams sp, int* status,
+    camp_cell_stats* stats, int* queue) {
   extern __shared__ double lds[];
+  const char* tab = stage_tables<kStage>(m, lds);
+  const int W = blockDim.x / kWave, wid = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+  const size_t stage_d = kStage ? (size_t)m.stage_bytes / 8 : 0;
+  double* base = lds + stage_d + wid * cell_doubles(m);
   const int np = m.n_part > m.R ? m.n_part : m.R;
-  WaveCell<NPL> W{m, lds, lds + m.Z, lds + m.Z + m.N, lds + m.Z + 2 * m.N,
-                  lds + m.Z + 2 * m.N + np, (int)threadIdx.x};
+  const WaveCell<NPL> Wc{m, Tabs{tab, m}, base, base + m.Z, base + m.Z + m.N,
+                         base + m.Z + 2 * m.N, base + m.Z + 2 * m.N + np, lane};
   if (!queue) {
-    const int cell = blockIdx.x;
-    if (cell < n_cells) solve_one_cell<NPL>(m, env, state, cell, sp, status, stats, W);
+    const int cell = blockIdx.x * W + wid;
+    if (cell < n_cells) solve_one_cell<NPL>(m, env, state, cell, sp, status, stats, Wc);
     return;
   }
   while (true) {
     int cell = 0;
-    if (threadIdx.x == 0) cell = atomicAdd(queue, 1);
+    if (lane == 0) cell = atomicAdd(queue, 1);
     cell = __shfl(cell, 0, kWave);
     if (cell >= n_cells) break;
-    solve_one_cell<NPL>(m, env, state, cell, sp, status, stats, W);
+    solve_one_cell<NPL>(m, env, state, cell, sp, status, stats, Wc);
   }
 }
 
+size_t wave_cell_bytes(const DevMech& m) {
+  const int np = m.n_part > m.R ? m.n_part : m.R;
+  return sizeof(double) * ((size_t)m.Z + 2 * (size_t)m.N + np + m.R);
+}
+
+size_t wave_lds_bytes(const DevMech& m) { return wave_cell_bytes(m); }
+
+// LDS bytes of a workgroup of `waves` cells, with or without the staged tables.
+size_t wave_wg_lds_bytes(const DevMech& m, int waves, bool stage) {
+  return (stage ? (size_t)m.stage_bytes : 0) + (size_t)waves * wave_cell_bytes(m);
+}
+
+hipError_t launch_bdf_wave(const DevMech& m, const DevEnv& env, double* state, int n_cells,
+                           const SolveParams& sp, int* status, camp_cell_stats* stats, int* queue,
+                           int grid, int waves, bool stage, hipStream_t stream) {
+  const size_t lds = wave_wg_lds_bytes(m, waves, stage);
+  const int npl = (m.N + kWave - 1) / kWave;
+  if (waves < 1 || waves > wave_max_waves(m.N)) return hipErrorInvalidValue;
+  if (stage && m.stage_bytes <= 0) return hipErrorInvalidValue;
+#define CAMP_WAVE_CASE(K)                                                                       \
+  case K: {                                                                                     \
+    const void* fn = stage ? (const void*)bdf_wave_kernel<K, true>                             \
+                           : (const void*)bdf_wave_kernel<K, false>;                           \
+    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds); \
+    if (e != hipSuccess) return e;                                                              \
+    if (stage)                                                                                  \
+      hipLaunchKernelGGL((bdf_wave_kernel<K, true>), dim3(grid), dim3(kWave * waves), lds, stream, \
+                         m, env, state, n_cells, sp, status, stats, queue);                     \
+    else                                                                                        \
+      hipLaunchKernelGGL((bdf_wave_kernel<K, false>), dim3(grid), dim3(kWave * waves), lds,    \
+                         stream, m, env, state, n_cells, sp, status, stats, queue);             \
+    return hipGetLastError();                                                                   \
+  }
+  switch (npl) {
+    CAMP_WAVE_CASE(1)
+    CAMP_WAVE_CASE(2)
+    CAMP_WAVE_CASE(3)
+    CAMP_WAVE_CASE(4)
+    CAMP_WAVE_CASE(5)
+    CAMP_WAVE_CASE(6)
+    CAMP_WAVE_CASE(7)
+    CAMP_WAVE_CASE(8)
+    CAMP_WAVE_CASE(9)
+    default:
+      return hipErrorInvalidValue;
+  }
+#undef CAMP_WAVE_CASE
+}
+
 // ---------------------------------------------------------------- single-step kernels
-// One wavefront per cell; the same device code as the fused engine, on row-major
-// [cells][...] arrays in user state order.
+// One wavefront per cell; the same device code as the fused engine (tables read from
+// global memory), on row-major [cells][...] arrays in user state order.
 
 template <int NPL>
 __global__ __launch_bounds__(kWave) void wave_step_kernel(DevMech m, int op, int n_cells,
@@ -507,15 +642,16 @@ __global__ __launch_bounds__(kWave) void wave_step_kernel(DevMech m, int op, int
                                                           double* out, double gamma) {
   extern __shared__ double lds[];
   const int np = m.n_part > m.R ? m.n_part : m.R;
-  WaveCell<NPL> W{m, lds, lds + m.Z, lds + m.Z + m.N, lds + m.Z + 2 * m.N,
-                  lds + m.Z + 2 * m.N + np, (int)threadIdx.x};
+  const WaveCell<NPL> W{m, Tabs{reinterpret_cast<const char*>(m.stage), m}, lds, lds + m.Z,
+                        lds + m.Z + m.N, lds + m.Z + 2 * m.N, lds + m.Z + 2 * m.N + np,
+                        (int)threadIdx.x};
   const int cell = blockIdx.x;
   if (cell >= n_cells) return;
   const int lane = threadIdx.x;
   if (op == 0 || op == 1) {  // forcing / Newton matrix from k and y
     for (int k = lane; k < m.R; k += kWave) W.kc[k] = kin[(size_t)cell * m.R + k];
     for (int t = lane; t < m.N; t += kWave) W.yl[t] = yin[(size_t)cell * m.N + m.perm[t]];
-    __syncthreads();
+    wave_sync();
     if (op == 0) {
       double f[NPL];
       W.forcing(f);
@@ -530,13 +666,13 @@ __global__ __launch_bounds__(kWave) void wave_step_kernel(DevMech m, int op, int
     }
   } else if (op == 2) {      // LU in place on out
     for (int s = lane; s < m.Z; s += kWave) W.M[s] = out[(size_t)cell * m.Z + s];
-    __syncthreads();
+    wave_sync();
     W.lu();
     for (int s = lane; s < m.Z; s += kWave) out[(size_t)cell * m.Z + s] = W.M[s];
   } else {                   // solve: kin = LU, out = b -> x
     for (int s = lane; s < m.Z; s += kWave) W.M[s] = kin[(size_t)cell * m.Z + s];
     for (int t = lane; t < m.N; t += kWave) W.xl[t] = out[(size_t)cell * m.N + m.perm[t]];
-    __syncthreads();
+    wave_sync();
     W.solve();
     for (int t = lane; t < m.N; t += kWave) out[(size_t)cell * m.N + m.perm[t]] = W.xl[t];
   }
@@ -562,44 +698,9 @@ hipError_t launch_rates_step(const DevMech& m, const DevEnv& env, int n_cells, d
   return hipGetLastError();
 }
 
-size_t wave_lds_bytes(const DevMech& m) {
-  const int np = m.n_part > m.R ? m.n_part : m.R;
-  return sizeof(double) * ((size_t)m.Z + 2 * (size_t)m.N + np + m.R);
-}
-
-hipError_t launch_bdf_wave(const DevMech& m, const DevEnv& env, double* state, int n_cells,
-                           const SolveParams& sp, int* status, camp_cell_stats* stats, int* queue,
-                           int grid, hipStream_t stream) {
-  const size_t lds = wave_lds_bytes(m);
-  const int npl = (m.N + kWave - 1) / kWave;
-#define CAMP_WAVE_CASE(K)                                                                      \
-  case K: {                                                                                    \
-    hipError_t e = hipFuncSetAttribute((const void*)bdf_wave_kernel<K>,                        \
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);   \
-    if (e != hipSuccess) return e;                                                             \
-    hipLaunchKernelGGL(bdf_wave_kernel<K>, dim3(grid), dim3(kWave), lds, stream, m, env, state, \
-                       n_cells, sp, status, stats, queue);                                     \
-    return hipGetLastError();                                                                  \
-  }
-  switch (npl) {
-    CAMP_WAVE_CASE(1)
-    CAMP_WAVE_CASE(2)
-    CAMP_WAVE_CASE(3)
-    CAMP_WAVE_CASE(4)
-    CAMP_WAVE_CASE(5)
-    CAMP_WAVE_CASE(6)
-    CAMP_WAVE_CASE(7)
-    CAMP_WAVE_CASE(8)
-    CAMP_WAVE_CASE(9)
-    default:
-      return hipErrorInvalidValue;
-  }
-#undef CAMP_WAVE_CASE
-}
-
 hipError_t launch_wave_step(const DevMech& m, int op, int n_cells, const double* kin,
                             const double* yin, double* out, double gamma, hipStream_t stream) {
-  const size_t lds = wave_lds_bytes(m);
+  const size_t lds = wave_cell_bytes(m);
   const int npl = (m.N + kWave - 1) / kWave;
   if (n_cells == 0) return hipSuccess;
 #define CAMP_STEP_CASE(K)                                                                      \

@@ -48,14 +48,6 @@ struct Task {
   int dst, diag, pbeg, pend;
 };
 
-// Tasks of one dependency level, grouped in passes of `width` lanes each: the lane l task
-// of pass p is tasks[(pass_begin + p) * width + l] (dst < 0: idle lane).
-struct WaveSchedule {
-  int width = 0;
-  std::vector<int> level_pass;   // [levels + 1] pass offsets
-  std::vector<Task> tasks;       // [passes * width]
-};
-
 struct Compiled {
   // sizes
   int n_state = 0, n_gas = 0, n_inst = 0, n_rxn = 0, n_ext = 0;
@@ -98,13 +90,23 @@ struct Compiled {
   int bwd_levels() const { return (int)bwd_level_ptr.size() - 1; }
 };
 
+// Compact copies of the latency-critical tables (reactant indices, CSR pattern with
+// level-ordered solve rows, Crout LU tasks and pairs) in one byte block, laid out so a
+// workgroup can copy it into LDS with 16-byte loads. 16-bit indices: requires N < 1023
+// (10-bit reactant fields) and Z <= 65535.
+struct StageBlock {
+  std::vector<uint8_t> bytes;
+  int off_rx = 0, off_col = 0, off_rowptr = 0, off_diag = 0;
+  int off_fwd_rows = 0, off_fwd_lptr = 0, off_bwd_rows = 0, off_bwd_lptr = 0;
+  int off_lu_tk = 0, off_lu_pr = 0, off_lu_lptr = 0;
+  int n_lu_tk = 0;
+  bool ok = false;   // false when the mechanism exceeds the 16-bit index ranges
+};
+
+StageBlock build_stage_block(const Compiled& C);
+
 // Returns an empty string on success, else the validation/compile error.
 std::string compile_mechanism(const camp_reaction* rxns, int n_rxn, const camp_species* sp,
                               int n_sp, const camp_phase* ph, int n_ph, Compiled& out);
-
-// Groups the tasks of each level into passes of `width` lanes, longest task first onto
-// the least-loaded lane, so that each pass's lanes carry similar work.
-WaveSchedule build_wave_schedule(const std::vector<Task>& tasks,
-                                 const std::vector<int>& level_ptr, int width);
 
 }  // namespace camp

@@ -21,6 +21,8 @@ struct Tuning {
   int engine = CAMP_ENGINE_FUSED_WAVE;
   int persistent = 1;        // wave engine: 1 = queue-driven persistent grid
   int grid_mult = 8;         // wave engine: workgroups per CU when persistent
+  int waves = 1;             // wave engine: wavefronts (cells) per workgroup
+  int stage = 1;             // wave engine: stage the index tables in LDS
   double ms = 0.0;           // measured trial time
 };
 
@@ -36,9 +38,13 @@ int hip_fail(hipError_t e, const char* what);
 
 // Launchers (defined in the engine files).
 size_t wave_lds_bytes(const DevMech& m);
+size_t wave_cell_bytes(const DevMech& m);
+size_t wave_wg_lds_bytes(const DevMech& m, int waves, bool stage);
+int wave_max_waves(int n_state);
 hipError_t launch_bdf_wave(const DevMech& m, const DevEnv& env, double* state, int n_cells,
                            const SolveParams& sp, int* status, camp_cell_stats* stats, int* queue,
-                           int grid, hipStream_t stream);
+                           int grid, int waves, bool stage, hipStream_t stream);
+constexpr size_t kLdsBytes = 160 * 1024;
 hipError_t launch_wave_step(const DevMech& m, int op, int n_cells, const double* kin,
                             const double* yin, double* out, double gamma, hipStream_t stream);
 hipError_t launch_rates_step(const DevMech& m, const DevEnv& env, int n_cells, double* k_out,
@@ -56,7 +62,7 @@ hipError_t launch_fill_int(int* p, int n, int v, hipStream_t stream);
 
 struct camp_mech {
   camp::Compiled C;
-  camp::WaveSchedule wlu, wfwd, wbwd;
+  camp::StageBlock stage;
   std::mutex mu;
   std::map<int, camp::DeviceTables> dev;            // per device id
   std::map<std::pair<int, int>, camp::Tuning> tune; // (device, cell bucket)
