@@ -26,6 +26,11 @@ constexpr double kNewtonDiverge = 2.0;
 // order 1 from y_n with the step cut by kRestartFactor.
 constexpr int kErrRestart = 3;
 constexpr double kRestartFactor = 0.1;
+// Inequality constraint y >= 0 (CVODE's constraint option, Hindmarsh et al. 2005): a
+// converged step with a component below -1 in weighted-tolerance units is rejected and
+// the step cut by this factor. Without it, undershoots of fast species drive the
+// bimolecular terms unstable and the step size collapses.
+constexpr double kConstraintFactor = 0.25;
 
 enum CellStatus : int { ST_OK = 0, ST_MAX_STEPS = 1, ST_H_MIN = 2, ST_ERR_FAIL = 3,
                         ST_NEWTON_FAIL = 4, ST_NONFINITE = 5 };

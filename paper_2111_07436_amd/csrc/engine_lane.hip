@@ -442,6 +442,18 @@ __device__ void lane_finish(const LaneCtx& C, int slot, int* new_step) {
     return;
   }
   S.force_lu[slot] = 0;
+  // positivity constraint (see kConstraintFactor): reject, never clip
+  int neg = 0;
+  for (int i = 0; i < m.N; ++i)
+    if (L.y(i) * L.w(i) < -1.0) neg = 1;
+  if (neg) {
+    S.st[slot].rejected++;
+    L.rescale(q, kConstraintFactor);
+    S.h[slot] = h * kConstraintFactor;
+    S.n_equal[slot] = 0;
+    S.phase[slot] = PH_IDLE;
+    return;
+  }
   const double err = lane_wrms_d_w(L, 1.0 / (q + 1));
   if (err > 1.0) {
     S.st[slot].rejected++;

@@ -400,6 +400,19 @@ __device__ __forceinline__ int integrate(const DevMech& m, double* yrow, const S
         continue;
       }
       force_lu = 0;
+      // positivity constraint: a converged solution more than one tolerance unit below
+      // zero is rejected and retried with a smaller step (values are never clipped)
+      int neg = 0;
+#pragma unroll
+      for (int i = 0; i < NPL; ++i)
+        if (lane + kWave * i < N && yv[i] * w[i] < -1.0) neg = 1;
+      if (wave_or(neg)) {
+        cs.rejected++;
+        rescale_hist(D, q, kConstraintFactor);
+        h *= kConstraintFactor;
+        n_equal = 0;
+        continue;
+      }
       double dq1[NPL];
 #pragma unroll
       for (int i = 0; i < NPL; ++i) dq1[i] = d[i] / (q + 1);
