@@ -255,8 +255,10 @@ typedef struct camp_server camp_server;
 int camp_serve_create(long long max_bytes, int max_inflight, camp_server** out);
 
 /* Submit a request on device-resident data (pointers stay owned by the caller and must
- * remain valid until the request completes). The request is queued if it does not fit
- * the memory budget. Returns a ticket (> 0). */
+ * remain valid until the request completes; the data must be ready, i.e. the stream that
+ * produced it synchronized, since requests run on the server's own streams). The request
+ * is queued if it does not fit the memory budget or no stream slot is free. Returns a
+ * ticket (> 0). Requests that overlap on the device never share arithmetic. */
 int camp_serve_submit(camp_server* srv, camp_mech* mech, int n_cells, double* d_state,
                       const camp_env* d_env, double dt, double rtol, double atol,
                       const camp_opts* opts, int* d_cell_status, long long* ticket);

@@ -291,7 +291,9 @@ Tuning default_tuning(const DevMech& dm, int n_cells) {
   return t;
 }
 
-int autotuned(camp_mech* mh, const DevMech& dm, int n_cells, Tuning* out);
+int autotuned(camp_mech* mh, const DevMech& dm, int n_cells, double* d_state,
+              const camp_env* d_env, const SolveParams& sp, const camp_opts* opts,
+              hipStream_t stream, Tuning* out);
 
 }  // namespace camp
 
@@ -382,7 +384,7 @@ int camp_solve_device(camp_mech* mh, int n_cells, double* d_state, const camp_en
   Tuning tu;
   const int engine = opts ? opts->engine : CAMP_ENGINE_AUTO;
   if (engine == CAMP_ENGINE_AUTO) {
-    rc = autotuned(mh, *dm, n_cells, &tu);
+    rc = autotuned(mh, *dm, n_cells, d_state, d_env, sp, opts, (hipStream_t)stream, &tu);
     if (rc != CAMP_OK) return rc;
   } else {
     tu = default_tuning(*dm, n_cells);

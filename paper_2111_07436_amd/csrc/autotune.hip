@@ -1,29 +1,221 @@
-// Autotuner: picks the engine and launch shape per (mechanism, device, cell-count bucket)
-// by timing short trials, and caches the choice.
+// Autotuner: picks the engine and launch shape per (mechanism, device, cell-count bucket).
+//
+// On the first call for a bucket it times short trials of each candidate on a copy of the
+// call's own first cells (the caller's arrays are never written by a trial) and caches
+// the fastest. Candidates: the wavefront engine with and without LDS-staged tables, 1..8
+// cells per workgroup, a persistent grid sized to the resident capacity or one workgroup
+// per cell batch; and the lane-per-cell fused engine. With CAMP_TUNE_CACHE set to a file
+// path, choices persist across processes (keyed by a hash of the compiled mechanism, the
+// device name and the bucket).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <fstream>
+#include <sstream>
+#include <vector>
 
 #include "runtime.hpp"
 
 namespace camp {
 
 Tuning default_tuning(const DevMech& dm, int n_cells);
+int solve_device_tuned(camp_mech* mh, const DevMech& dm, int n_cells, double* d_state,
+                       const camp_env* d_env, const SolveParams& sp, const camp_opts* opts,
+                       int* d_status, camp_cell_stats* d_stats, hipStream_t stream, const Tuning& tu);
 
-int autotuned(camp_mech* mh, const DevMech& dm, int n_cells, Tuning* out) {
+namespace {
+
+uint64_t fnv(uint64_t h, const void* p, size_t n) {
+  const unsigned char* b = static_cast<const unsigned char*>(p);
+  for (size_t i = 0; i < n; ++i) {
+    h ^= b[i];
+    h *= 1099511628211ull;
+  }
+  return h;
+}
+
+uint64_t mech_hash(const camp_mech* mh) {
+  const Compiled& C = mh->C;
+  uint64_t h = 1469598103934665603ull;
+  h = fnv(h, &C.n_state, sizeof(int));
+  h = fnv(h, &C.n_rxn, sizeof(int));
+  h = fnv(h, mh->stage.bytes.data(), mh->stage.bytes.size());
+  for (const RateSpec& r : C.rate) h = fnv(h, &r, sizeof(RateSpec));
+  h = fnv(h, C.term_coef.data(), 8 * C.term_coef.size());
+  return h;
+}
+
+std::string device_name() {
+  int dev = 0;
+  hipGetDevice(&dev);
+  hipDeviceProp_t p;
+  if (hipGetDeviceProperties(&p, dev) != hipSuccess) return "unknown";
+  std::string s = p.gcnArchName;
+  for (char& c : s)
+    if (c == ' ') c = '_';
+  return s;
+}
+
+std::string cache_key(const camp_mech* mh, int bucket, const SolveParams& sp) {
+  std::ostringstream k;
+  k << std::hex << mech_hash(mh) << std::dec << ' ' << device_name() << ' ' << bucket << ' '
+    << sp.full_newton;
+  return k.str();
+}
+
+bool load_cached(const std::string& key, Tuning* t) {
+  const char* path = std::getenv("CAMP_TUNE_CACHE");
+  if (!path || !*path) return false;
+  std::ifstream f(path);
+  std::string line;
+  bool found = false;
+  while (std::getline(f, line)) {
+    if (line.compare(0, key.size(), key) != 0 || line.size() <= key.size() || line[key.size()] != '|')
+      continue;
+    std::istringstream v(line.substr(key.size() + 1));
+    Tuning x;
+    if (v >> x.engine >> x.persistent >> x.grid_mult >> x.waves >> x.stage >> x.ms) {
+      *t = x;
+      found = true;   // last entry wins
+    }
+  }
+  return found;
+}
+
+void store_cached(const std::string& key, const Tuning& t) {
+  const char* path = std::getenv("CAMP_TUNE_CACHE");
+  if (!path || !*path) return;
+  std::ofstream f(path, std::ios::app);
+  f << key << '|' << t.engine << ' ' << t.persistent << ' ' << t.grid_mult << ' ' << t.waves << ' '
+    << t.stage << ' ' << t.ms << '\n';
+}
+
+int n_cus_dev() {
+  int dev = 0, cus = 0;
+  hipGetDevice(&dev);
+  hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  return cus > 0 ? cus : 256;
+}
+
+std::vector<Tuning> candidates(const DevMech& dm) {
+  std::vector<Tuning> out;
+  const bool wave_ok = (dm.N + kWave - 1) / kWave <= 9 && dm.stage;
+  if (wave_ok) {
+    const int wmax = wave_max_waves(dm.N);
+    for (int stage = 1; stage >= 0; --stage)
+      for (int w : {1, 2, 4, 8}) {
+        if (w > wmax) continue;
+        const size_t b = wave_wg_lds_bytes(dm, w, stage != 0);
+        if (b > kLdsBytes) continue;
+        const int wgs = (int)(kLdsBytes / b);   // resident workgroups per CU by LDS
+        Tuning t;
+        t.engine = CAMP_ENGINE_FUSED_WAVE;
+        t.waves = w;
+        t.stage = stage;
+        t.persistent = 1;
+        t.grid_mult = std::max(1, std::min(wgs, std::max(1, wmax / w)));
+        out.push_back(t);
+        if (w == 1 || w == 8) {
+          Tuning np = t;
+          np.persistent = 0;
+          out.push_back(np);
+        }
+      }
+  }
+  // The lane-per-cell engine only competes when LDS holds at most two cells per CU.
+  const size_t cell = wave_wg_lds_bytes(dm, 1, false);
+  if (!wave_ok || cell == 0 || kLdsBytes / cell <= 2) {
+    Tuning lane;
+    lane.engine = CAMP_ENGINE_FUSED_LANE;
+    out.push_back(lane);
+  }
+  return out;
+}
+
+}  // namespace
+
+int autotuned(camp_mech* mh, const DevMech& dm, int n_cells, double* d_state,
+              const camp_env* d_env, const SolveParams& sp, const camp_opts* opts,
+              hipStream_t stream, Tuning* out) {
   int device = 0;
   hipGetDevice(&device);
   const int bucket = n_cells <= 1 ? 0 : (int)std::ceil(std::log2((double)n_cells));
-  std::lock_guard<std::mutex> g(mh->mu);
-  auto key = std::make_pair(device, bucket);
-  auto it = mh->tune.find(key);
-  if (it != mh->tune.end()) {
-    *out = it->second;
+  const auto key = std::make_pair(device, bucket * 2 + sp.full_newton);
+  {
+    std::lock_guard<std::mutex> g(mh->mu);
+    auto it = mh->tune.find(key);
+    if (it != mh->tune.end()) {
+      *out = it->second;
+      return CAMP_OK;
+    }
+  }
+  const std::string ckey = cache_key(mh, bucket, sp);
+  Tuning best;
+  if (load_cached(ckey, &best)) {
+    std::lock_guard<std::mutex> g(mh->mu);
+    mh->tune[key] = best;
+    *out = best;
     return CAMP_OK;
   }
-  Tuning t = default_tuning(dm, n_cells);
-  mh->tune[key] = t;
-  *out = t;
+
+  // Trial on a copy of the first cells of this call.
+  const int cus = n_cus_dev();
+  const int trial = std::min(n_cells, std::max(4096, cus * 32));
+  const size_t sbytes = sizeof(double) * (size_t)trial * dm.N;
+  char* buf = nullptr;
+  hipError_t e = hipMallocAsync((void**)&buf, 2 * sbytes + 4 * (size_t)trial + 256, stream);
+  if (e != hipSuccess) return hip_fail(e, "hipMallocAsync(autotune)");
+  double* src = reinterpret_cast<double*>(buf);
+  double* work = reinterpret_cast<double*>(buf + sbytes);
+  int* st = reinterpret_cast<int*>(buf + 2 * sbytes);
+  e = hipMemcpyAsync(src, d_state, sbytes, hipMemcpyDeviceToDevice, stream);
+  hipEvent_t a = nullptr, b = nullptr;
+  if (e == hipSuccess) e = hipEventCreate(&a);
+  if (e == hipSuccess) e = hipEventCreate(&b);
+  best = default_tuning(dm, n_cells);
+  best.ms = 1e30;
+  if (e == hipSuccess) {
+    for (Tuning t : candidates(dm)) {
+      // up to two timed runs on identical copies (min); a candidate far slower than the
+      // best so far is not run again
+      float best_ms = 1e30f;
+      int rc = CAMP_OK;
+      for (int rep = 0; rep < 2 && rc == CAMP_OK; ++rep) {
+        if (hipMemcpyAsync(work, src, sbytes, hipMemcpyDeviceToDevice, stream) != hipSuccess) {
+          rc = CAMP_EDEVICE;
+          break;
+        }
+        hipEventRecord(a, stream);
+        rc = solve_device_tuned(mh, dm, trial, work, d_env, sp, opts, st, nullptr, stream, t);
+        hipEventRecord(b, stream);
+        if (hipEventSynchronize(b) != hipSuccess) rc = CAMP_EDEVICE;
+        float ms = 0.f;
+        if (rc == CAMP_OK) hipEventElapsedTime(&ms, a, b);
+        best_ms = std::min(best_ms, ms);
+        if (ms > 2.0 * best.ms) break;
+      }
+      if (rc != CAMP_OK) continue;   // candidate not launchable for this mechanism
+      t.ms = best_ms;
+      if (t.ms < best.ms) best = t;
+    }
+  }
+  if (a) hipEventDestroy(a);
+  if (b) hipEventDestroy(b);
+  hipFreeAsync(buf, stream);
+  hipStreamSynchronize(stream);
+  if (best.ms >= 1e30) {
+    best = default_tuning(dm, n_cells);
+    best.ms = 0.0;
+  } else {
+    store_cached(ckey, best);
+  }
+  std::lock_guard<std::mutex> g(mh->mu);
+  mh->tune[key] = best;
+  *out = best;
   return CAMP_OK;
 }
 
