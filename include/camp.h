@@ -189,7 +189,9 @@ typedef struct {
   int use_graph;        /* PLAIN: 1 = replay a captured hipGraph of each chunk of     */
                         /* step-attempt launches                                      */
   int waves_per_wg;     /* FUSED_WAVE: wavefronts (cells) per workgroup 1..8, 0 = auto */
-  int stage_tables;     /* FUSED_WAVE: 1 = index tables in LDS, 0 = global, -1 = auto  */
+  int stage_tables;     /* FUSED_WAVE tables in LDS: 0 = none (global), 1 = sparse-index */
+                        /* tables, 2 = all (also forcing terms and Jacobian map),      */
+                        /* -1 = auto                                                   */
   int full_newton;      /* 0 (default): Newton with Jacobian reuse; a cell that fails   */
                         /* (status 1-4) is integrated again from its input with full    */
                         /* Newton. 1: full Newton (fresh Jacobian and LU every iteration)*/

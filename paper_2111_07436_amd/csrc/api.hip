@@ -139,6 +139,14 @@ int upload(camp_mech* mh, int device, DeviceTables& out) {
   d.so_lu_tk = sb.off_lu_tk;
   d.so_lu_pr = sb.off_lu_pr;
   d.so_lu_lptr = sb.off_lu_lptr;
+  d.stage_core_bytes = sb.ok ? sb.core_bytes : 0;
+  d.so_term_ptr = sb.off_term_ptr;
+  d.so_term_rxn = sb.off_term_rxn;
+  d.so_term_coef = sb.off_term_coef;
+  d.so_jc_ptr = sb.off_jc_ptr;
+  d.so_jc_part = sb.off_jc_part;
+  d.so_jc_coef = sb.off_jc_coef;
+  d.so_is_diag = sb.off_is_diag;
   out.device = device;
   out.blob = blob;
   out.bytes = total;
@@ -238,7 +246,7 @@ int solve_device_tuned(camp_mech* mh, const DevMech& dm, int n_cells, double* d_
       return CAMP_EINVAL;
     }
     const int waves = std::max(1, tu.waves);
-    const bool stage = tu.stage != 0;
+    const int stage = std::max(0, std::min(2, tu.stage));
     if (wave_wg_lds_bytes(dm, waves, stage) > kLdsBytes) {
       set_error("mechanism does not fit the wavefront engine's LDS budget");
       return CAMP_EINVAL;
@@ -265,22 +273,23 @@ int solve_device_tuned(camp_mech* mh, const DevMech& dm, int n_cells, double* d_
 }
 
 // Occupancy-driven default: the largest number of wavefronts per workgroup (<= 8) such that
-// the workgroups resident on one CU hold the most cells, preferring staged tables.
+// the workgroups resident on one CU hold the most cells, preferring the most tables staged.
 Tuning default_tuning(const DevMech& dm, int n_cells) {
   Tuning t;
   const bool fits_wave = (dm.N + kWave - 1) / kWave <= 9 && dm.stage &&
-                         wave_wg_lds_bytes(dm, 1, false) <= kLdsBytes;
+                         wave_wg_lds_bytes(dm, 1, 0) <= kLdsBytes;
   t.engine = fits_wave ? CAMP_ENGINE_FUSED_WAVE : CAMP_ENGINE_FUSED_LANE;
   t.persistent = 1;
   int best_cells = 0;
   const int wmax = wave_max_waves(dm.N);   // also the resident wavefronts per CU by VGPRs
-  for (int stage = 1; stage >= 0; --stage)
+  t.stage = -1;
+  for (int stage = 2; stage >= 0; --stage)
     for (int w = 1; w <= wmax; ++w) {
-      const size_t b = wave_wg_lds_bytes(dm, w, stage != 0);
+      const size_t b = wave_wg_lds_bytes(dm, w, stage);
       if (b > kLdsBytes) break;
       const int wgs = (int)(kLdsBytes / b);
       const int cells = std::min(wgs * w, wmax);
-      if (cells > best_cells || (cells == best_cells && stage && !t.stage)) {
+      if (cells > best_cells) {
         best_cells = cells;
         t.waves = w;
         t.stage = stage;
@@ -394,7 +403,7 @@ int camp_solve_device(camp_mech* mh, int n_cells, double* d_state, const camp_en
     if (opts->persistent >= 0) tu.persistent = opts->persistent ? 1 : 0;
     if (opts->wg_per_cu > 0) tu.grid_mult = opts->wg_per_cu;
     if (opts->waves_per_wg > 0) tu.waves = std::min(opts->waves_per_wg, 8);
-    if (opts->stage_tables >= 0) tu.stage = opts->stage_tables ? 1 : 0;
+    if (opts->stage_tables >= 0) tu.stage = std::min(opts->stage_tables, 2);
   }
   return solve_device_tuned(mh, *dm, n_cells, d_state, d_env, sp, opts, d_status, d_stats,
                             (hipStream_t)stream, tu);

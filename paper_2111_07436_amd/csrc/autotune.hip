@@ -2,7 +2,8 @@
 //
 // On the first call for a bucket it times short trials of each candidate on a copy of the
 // call's own first cells (the caller's arrays are never written by a trial) and caches
-// the fastest. Candidates: the wavefront engine with and without LDS-staged tables, 1..8
+// the fastest. Candidates: the wavefront engine at the two deepest LDS table-staging levels
+// that fit, 1..8
 // cells per workgroup, a persistent grid sized to the resident capacity or one workgroup
 // per cell batch; and the lane-per-cell fused engine. With CAMP_TUNE_CACHE set to a file
 // path, choices persist across processes (keyed by a hash of the compiled mechanism, the
@@ -106,11 +107,13 @@ std::vector<Tuning> candidates(const DevMech& dm) {
   const bool wave_ok = (dm.N + kWave - 1) / kWave <= 9 && dm.stage;
   if (wave_ok) {
     const int wmax = wave_max_waves(dm.N);
-    for (int stage = 1; stage >= 0; --stage)
-      for (int w : {1, 2, 4, 8}) {
-        if (w > wmax) continue;
-        const size_t b = wave_wg_lds_bytes(dm, w, stage != 0);
+    for (int w : {1, 2, 4, 8}) {
+      if (w > wmax) continue;
+      int tried = 0;   // the two most-staged levels that fit
+      for (int stage = 2; stage >= 0 && tried < 2; --stage) {
+        const size_t b = wave_wg_lds_bytes(dm, w, stage);
         if (b > kLdsBytes) continue;
+        ++tried;
         const int wgs = (int)(kLdsBytes / b);   // resident workgroups per CU by LDS
         Tuning t;
         t.engine = CAMP_ENGINE_FUSED_WAVE;
@@ -125,9 +128,10 @@ std::vector<Tuning> candidates(const DevMech& dm) {
           out.push_back(np);
         }
       }
+    }
   }
   // The lane-per-cell engine only competes when LDS holds at most two cells per CU.
-  const size_t cell = wave_wg_lds_bytes(dm, 1, false);
+  const size_t cell = wave_wg_lds_bytes(dm, 1, 0);
   if (!wave_ok || cell == 0 || kLdsBytes / cell <= 2) {
     Tuning lane;
     lane.engine = CAMP_ENGINE_FUSED_LANE;

@@ -664,6 +664,21 @@ StageBlock build_stage_block(const Compiled& C) {
   sb.off_lu_pr = put(pr.data(), 4 * pr.size());
   sb.off_lu_lptr = put(llp.data(), 4 * llp.size());
   b.resize((b.size() + 15) / 16 * 16);
+  sb.core_bytes = (int)b.size();
+  // extension: forcing terms and Jacobian contributions
+  if (C.n_partials >= 65536 || R >= 65536) return StageBlock{};
+  std::vector<uint32_t> tp(C.term_ptr.begin(), C.term_ptr.end()), jp(C.jc_ptr.begin(), C.jc_ptr.end());
+  std::vector<uint16_t> trx(C.term_rxn.begin(), C.term_rxn.end()), jpart(C.jc_part.begin(), C.jc_part.end());
+  std::vector<uint8_t> isd(Z, 0);
+  for (int t = 0; t < N; ++t) isd[C.diag[t]] = 1;
+  sb.off_term_coef = put(C.term_coef.data(), 8 * C.term_coef.size());
+  sb.off_jc_coef = put(C.jc_coef.data(), 8 * C.jc_coef.size());
+  sb.off_term_ptr = put(tp.data(), 4 * tp.size());
+  sb.off_jc_ptr = put(jp.data(), 4 * jp.size());
+  sb.off_term_rxn = put(trx.data(), 2 * trx.size());
+  sb.off_jc_part = put(jpart.data(), 2 * jpart.size());
+  sb.off_is_diag = put(isd.data(), isd.size());
+  b.resize((b.size() + 15) / 16 * 16);
   sb.ok = true;
   return sb;
 }

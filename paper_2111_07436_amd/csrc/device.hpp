@@ -49,9 +49,11 @@ struct DevMech {
   const int2* bwd_pair;
   // compact latency-critical tables (one block, byte offsets; see StageBlock)
   const uint8_t* stage;
-  int stage_bytes;
+  int stage_bytes;        // whole block
+  int stage_core_bytes;   // core prefix (index tables of the sparse steps)
   int so_rx, so_col, so_rowptr, so_diag, so_fwd_rows, so_fwd_lptr, so_bwd_rows, so_bwd_lptr;
   int so_lu_tk, so_lu_pr, so_lu_lptr;
+  int so_term_ptr, so_term_rxn, so_term_coef, so_jc_ptr, so_jc_part, so_jc_coef, so_is_diag;
 };
 
 // Per-cell environment (device pointers, row-major [cells] / [cells][n_inst]).

@@ -32,10 +32,19 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Accessors of the compact table block, in LDS (staged) or in global memory.
+// Accessors of the compact table block: the core tables through `b`, the forcing-term and
+// Jacobian-contribution extension through `e`; each base is LDS (staged) or global memory.
 struct Tabs {
   const char* b;
+  const char* e;
   const DevMech& m;
+  __device__ int term_ptr(int t) const { return (int)reinterpret_cast<const uint32_t*>(e + m.so_term_ptr)[t]; }
+  __device__ int term_rxn(int q) const { return reinterpret_cast<const uint16_t*>(e + m.so_term_rxn)[q]; }
+  __device__ double term_coef(int q) const { return reinterpret_cast<const double*>(e + m.so_term_coef)[q]; }
+  __device__ int jc_ptr(int s) const { return (int)reinterpret_cast<const uint32_t*>(e + m.so_jc_ptr)[s]; }
+  __device__ int jc_part(int q) const { return reinterpret_cast<const uint16_t*>(e + m.so_jc_part)[q]; }
+  __device__ double jc_coef(int q) const { return reinterpret_cast<const double*>(e + m.so_jc_coef)[q]; }
+  __device__ bool is_diag(int s) const { return reinterpret_cast<const uint8_t*>(e + m.so_is_diag)[s] != 0; }
   __device__ uint32_t rx(int k) const { return reinterpret_cast<const uint32_t*>(b + m.so_rx)[k]; }
   __device__ int col(int q) const { return reinterpret_cast<const uint16_t*>(b + m.so_col)[q]; }
   __device__ int rowptr(int t) const { return reinterpret_cast<const uint16_t*>(b + m.so_rowptr)[t]; }
@@ -88,9 +97,9 @@ struct WaveCell {
       const int t = lane + kWave * i;
       double acc = 0.0;
       if (t < m.N) {
-        const int q0 = m.term_ptr[t], q1 = m.term_ptr[t + 1];
+        const int q0 = tb.term_ptr(t), q1 = tb.term_ptr(t + 1);
 #pragma unroll 4
-        for (int q = q0; q < q1; ++q) acc += m.term_coef[q] * P[m.term_rxn[q]];
+        for (int q = q0; q < q1; ++q) acc += tb.term_coef(q) * P[tb.term_rxn(q)];
       }
       f[i] = acc;
     }
@@ -113,10 +122,10 @@ struct WaveCell {
     wave_sync();
     for (int s = lane; s < m.Z; s += kWave) {
       double acc = 0.0;
-      const int q0 = m.jc_ptr[s], q1 = m.jc_ptr[s + 1];
+      const int q0 = tb.jc_ptr(s), q1 = tb.jc_ptr(s + 1);
 #pragma unroll 4
-      for (int q = q0; q < q1; ++q) acc += m.jc_coef[q] * P[m.jc_part[q]];
-      M[s] = (m.is_diag[s] ? 1.0 : 0.0) - c * acc;
+      for (int q = q0; q < q1; ++q) acc += tb.jc_coef(q) * P[tb.jc_part(q)];
+      M[s] = (tb.is_diag(s) ? 1.0 : 0.0) - c * acc;
     }
     wave_sync();
   }
@@ -131,6 +140,7 @@ struct WaveCell {
         const int dst = t.x & 0xFFFF, dgs = t.x >> 16;
         const int pb = t.y & 0xFFFFF, cnt = t.y >> 20;
         double acc = M[dst];
+#pragma unroll 4
         for (int q = 0; q < cnt; ++q) {
           const uint32_t pr = tb.lu_pr(pb + q);
           acc -= M[pr & 0xFFFF] * M[pr >> 16];
@@ -161,6 +171,7 @@ struct WaveCell {
         const int t = tb.fwd_row(i);
         double acc = xl[t];
         const int q1 = tb.dg(t);
+#pragma unroll 4
         for (int q = tb.rowptr(t); q < q1; ++q) acc -= M[q] * xl[tb.col(q)];
         xl[t] = acc;
       }
@@ -172,6 +183,7 @@ struct WaveCell {
         const int t = tb.bwd_row(i);
         double acc = xl[t];
         const int d = tb.dg(t), q1 = tb.rowptr(t + 1);
+#pragma unroll 4
         for (int q = d + 1; q < q1; ++q) acc -= M[q] * xl[tb.col(q)];
         xl[t] = acc / M[d];
       }
@@ -548,15 +560,24 @@ __device__ inline size_t cell_doubles(const DevMech& m) {
   return (size_t)m.Z + 2 * (size_t)m.N + np + m.R;
 }
 
-// Copies the compact table block into LDS (16-byte units) and returns its base.
-template <bool kStage>
-__device__ __forceinline__ const char* stage_tables(const DevMech& m, double* lds) {
-  if (!kStage) return reinterpret_cast<const char*>(m.stage);
+// Bytes of the table block staged in LDS at staging level `stage`: 0 none, 1 the core
+// index tables, 2 the whole block (core + forcing terms + Jacobian contributions).
+__host__ __device__ inline int staged_bytes(const DevMech& m, int stage) {
+  return stage == 2 ? m.stage_bytes : stage == 1 ? m.stage_core_bytes : 0;
+}
+
+// Copies the staged part of the table block into LDS (16-byte units).
+template <int kStage>
+__device__ __forceinline__ Tabs stage_tables(const DevMech& m, double* lds) {
+  const char* g = reinterpret_cast<const char*>(m.stage);
+  if (kStage == 0) return Tabs{g, g, m};
   const uint4* src = reinterpret_cast<const uint4*>(m.stage);
   uint4* dst = reinterpret_cast<uint4*>(lds);
-  for (int i = threadIdx.x; i < m.stage_bytes / 16; i += blockDim.x) dst[i] = src[i];
+  const int n16 = staged_bytes(m, kStage) / 16;
+  for (int i = threadIdx.x; i < n16; i += blockDim.x) dst[i] = src[i];
   __syncthreads();
-  return reinterpret_cast<const char*>(lds);
+  const char* l = reinterpret_cast<const char*>(lds);
+  return Tabs{l, kStage == 2 ? l : g, m};
 }
 
 }  // namespace
@@ -570,17 +591,16 @@ int wave_max_waves(int n_state) { return (n_state + kWave - 1) / kWave <= 3 ? 8 
 
 // blockDim.x = 64 * W: W wavefronts, one cell each. queue != nullptr: persistent grid
 // pulling cells from the counter; else cell = blockIdx.x * W + wavefront.
-template <int NPL, bool kStage>
+template <int NPL, int kStage>
 __global__ __launch_bounds__(kWave * max_waves_per_wg<NPL>()) void bdf_wave_kernel(
     DevMech m, DevEnv env, double* state, int n_cells, SolveParams sp, int* status,
     camp_cell_stats* stats, int* queue) {
   extern __shared__ double lds[];
-  const char* tab = stage_tables<kStage>(m, lds);
+  const Tabs tab = stage_tables<kStage>(m, lds);
   const int W = blockDim.x / kWave, wid = threadIdx.x / kWave, lane = threadIdx.x % kWave;
-  const size_t stage_d = kStage ? (size_t)m.stage_bytes / 8 : 0;
-  double* base = lds + stage_d + wid * cell_doubles(m);
+  double* base = lds + staged_bytes(m, kStage) / 8 + wid * cell_doubles(m);
   const int np = m.n_part > m.R ? m.n_part : m.R;
-  const WaveCell<NPL> Wc{m, Tabs{tab, m}, base, base + m.Z, base + m.Z + m.N,
+  const WaveCell<NPL> Wc{m, tab, base, base + m.Z, base + m.Z + m.N,
                          base + m.Z + 2 * m.N, base + m.Z + 2 * m.N + np, lane};
   if (!queue) {
     const int cell = blockIdx.x * W + wid;
@@ -603,46 +623,55 @@ size_t wave_cell_bytes(const DevMech& m) {
 
 size_t wave_lds_bytes(const DevMech& m) { return wave_cell_bytes(m); }
 
-// LDS bytes of a workgroup of `waves` cells, with or without the staged tables.
-size_t wave_wg_lds_bytes(const DevMech& m, int waves, bool stage) {
-  return (stage ? (size_t)m.stage_bytes : 0) + (size_t)waves * wave_cell_bytes(m);
+// LDS bytes of a workgroup of `waves` cells at table staging level `stage` (0, 1, 2).
+size_t wave_wg_lds_bytes(const DevMech& m, int waves, int stage) {
+  return (size_t)staged_bytes(m, stage) + (size_t)waves * wave_cell_bytes(m);
+}
+
+template <int NPL, int kStage>
+hipError_t launch_wave_npl(const DevMech& m, const DevEnv& env, double* state, int n_cells,
+                           const SolveParams& sp, int* status, camp_cell_stats* stats, int* queue,
+                           int grid, int waves, size_t lds, hipStream_t stream) {
+  hipError_t e = hipFuncSetAttribute((const void*)bdf_wave_kernel<NPL, kStage>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((bdf_wave_kernel<NPL, kStage>), dim3(grid), dim3(kWave * waves), lds, stream,
+                     m, env, state, n_cells, sp, status, stats, queue);
+  return hipGetLastError();
+}
+
+template <int NPL>
+hipError_t launch_wave_stage(const DevMech& m, const DevEnv& env, double* state, int n_cells,
+                             const SolveParams& sp, int* status, camp_cell_stats* stats,
+                             int* queue, int grid, int waves, int stage, size_t lds,
+                             hipStream_t stream) {
+  switch (stage) {
+    case 0: return launch_wave_npl<NPL, 0>(m, env, state, n_cells, sp, status, stats, queue, grid, waves, lds, stream);
+    case 1: return launch_wave_npl<NPL, 1>(m, env, state, n_cells, sp, status, stats, queue, grid, waves, lds, stream);
+    case 2: return launch_wave_npl<NPL, 2>(m, env, state, n_cells, sp, status, stats, queue, grid, waves, lds, stream);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 hipError_t launch_bdf_wave(const DevMech& m, const DevEnv& env, double* state, int n_cells,
                            const SolveParams& sp, int* status, camp_cell_stats* stats, int* queue,
-                           int grid, int waves, bool stage, hipStream_t stream) {
+                           int grid, int waves, int stage, hipStream_t stream) {
   const size_t lds = wave_wg_lds_bytes(m, waves, stage);
   const int npl = (m.N + kWave - 1) / kWave;
   if (waves < 1 || waves > wave_max_waves(m.N)) return hipErrorInvalidValue;
-  if (stage && m.stage_bytes <= 0) return hipErrorInvalidValue;
-#define CAMP_WAVE_CASE(K)                                                                       \
-  case K: {                                                                                     \
-    const void* fn = stage ? (const void*)bdf_wave_kernel<K, true>                             \
-                           : (const void*)bdf_wave_kernel<K, false>;                           \
-    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds); \
-    if (e != hipSuccess) return e;                                                              \
-    if (stage)                                                                                  \
-      hipLaunchKernelGGL((bdf_wave_kernel<K, true>), dim3(grid), dim3(kWave * waves), lds, stream, \
-                         m, env, state, n_cells, sp, status, stats, queue);                     \
-    else                                                                                        \
-      hipLaunchKernelGGL((bdf_wave_kernel<K, false>), dim3(grid), dim3(kWave * waves), lds,    \
-                         stream, m, env, state, n_cells, sp, status, stats, queue);             \
-    return hipGetLastError();                                                                   \
-  }
+  if (stage < 0 || stage > 2 || !m.stage) return hipErrorInvalidValue;
   switch (npl) {
-    CAMP_WAVE_CASE(1)
-    CAMP_WAVE_CASE(2)
-    CAMP_WAVE_CASE(3)
-    CAMP_WAVE_CASE(4)
-    CAMP_WAVE_CASE(5)
-    CAMP_WAVE_CASE(6)
-    CAMP_WAVE_CASE(7)
-    CAMP_WAVE_CASE(8)
-    CAMP_WAVE_CASE(9)
-    default:
-      return hipErrorInvalidValue;
+    case 1: return launch_wave_stage<1>(m, env, state, n_cells, sp, status, stats, queue, grid, waves, stage, lds, stream);
+    case 2: return launch_wave_stage<2>(m, env, state, n_cells, sp, status, stats, queue, grid, waves, stage, lds, stream);
+    case 3: return launch_wave_stage<3>(m, env, state, n_cells, sp, status, stats, queue, grid, waves, stage, lds, stream);
+    case 4: return launch_wave_stage<4>(m, env, state, n_cells, sp, status, stats, queue, grid, waves, stage, lds, stream);
+    case 5: return launch_wave_stage<5>(m, env, state, n_cells, sp, status, stats, queue, grid, waves, stage, lds, stream);
+    case 6: return launch_wave_stage<6>(m, env, state, n_cells, sp, status, stats, queue, grid, waves, stage, lds, stream);
+    case 7: return launch_wave_stage<7>(m, env, state, n_cells, sp, status, stats, queue, grid, waves, stage, lds, stream);
+    case 8: return launch_wave_stage<8>(m, env, state, n_cells, sp, status, stats, queue, grid, waves, stage, lds, stream);
+    case 9: return launch_wave_stage<9>(m, env, state, n_cells, sp, status, stats, queue, grid, waves, stage, lds, stream);
+    default: return hipErrorInvalidValue;
   }
-#undef CAMP_WAVE_CASE
 }
 
 // ---------------------------------------------------------------- single-step kernels
@@ -655,7 +684,8 @@ __global__ __launch_bounds__(kWave) void wave_step_kernel(DevMech m, int op, int
                                                           double* out, double gamma) {
   extern __shared__ double lds[];
   const int np = m.n_part > m.R ? m.n_part : m.R;
-  const WaveCell<NPL> W{m, Tabs{reinterpret_cast<const char*>(m.stage), m}, lds, lds + m.Z,
+  const char* g = reinterpret_cast<const char*>(m.stage);
+  const WaveCell<NPL> W{m, Tabs{g, g, m}, lds, lds + m.Z,
                         lds + m.Z + m.N, lds + m.Z + 2 * m.N, lds + m.Z + 2 * m.N + np,
                         (int)threadIdx.x};
   const int cell = blockIdx.x;

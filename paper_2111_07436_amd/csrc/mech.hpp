@@ -94,11 +94,17 @@ struct Compiled {
 // level-ordered solve rows, Crout LU tasks and pairs) in one byte block, laid out so a
 // workgroup can copy it into LDS with 16-byte loads. 16-bit indices: requires N < 1023
 // (10-bit reactant fields) and Z <= 65535.
+// The block has a core part (the above) followed by an extension with the forcing terms
+// and Jacobian contributions (term_ptr/jc_ptr u32, rxn/partial u16, coef f64, is_diag u8),
+// so a workgroup may stage only the core when the whole block does not fit.
 struct StageBlock {
   std::vector<uint8_t> bytes;
+  int core_bytes = 0;
   int off_rx = 0, off_col = 0, off_rowptr = 0, off_diag = 0;
   int off_fwd_rows = 0, off_fwd_lptr = 0, off_bwd_rows = 0, off_bwd_lptr = 0;
   int off_lu_tk = 0, off_lu_pr = 0, off_lu_lptr = 0;
+  int off_term_ptr = 0, off_term_rxn = 0, off_term_coef = 0;
+  int off_jc_ptr = 0, off_jc_part = 0, off_jc_coef = 0, off_is_diag = 0;
   int n_lu_tk = 0;
   bool ok = false;   // false when the mechanism exceeds the 16-bit index ranges
 };
