@@ -129,16 +129,19 @@ int upload(camp_mech* mh, int device, DeviceTables& out) {
   d.stage = sb.ok ? (const uint8_t*)(b + o_stage) : nullptr;
   d.stage_bytes = sb.ok ? (int)sb.bytes.size() : 0;
   d.so_rx = sb.off_rx;
-  d.so_col = sb.off_col;
-  d.so_rowptr = sb.off_rowptr;
   d.so_diag = sb.off_diag;
-  d.so_fwd_rows = sb.off_fwd_rows;
-  d.so_fwd_lptr = sb.off_fwd_lptr;
-  d.so_bwd_rows = sb.off_bwd_rows;
-  d.so_bwd_lptr = sb.off_bwd_lptr;
-  d.so_lu_tk = sb.off_lu_tk;
-  d.so_lu_pr = sb.off_lu_pr;
-  d.so_lu_lptr = sb.off_lu_lptr;
+  d.so_sf = sb.off_sf;
+  d.so_sf_lp = sb.off_sf_lp;
+  d.so_sb = sb.off_sb;
+  d.so_sb_lp = sb.off_sb_lp;
+  d.so_lt = sb.off_lt;
+  d.so_lt_lp = sb.off_lt_lp;
+  d.so_lf = sb.off_lf;
+  d.so_lf_lp = sb.off_lf_lp;
+  d.so_us = sb.off_us;
+  d.n_sf_lev = sb.n_sf_lev;
+  d.n_sb_lev = sb.n_sb_lev;
+  d.n_us = sb.n_us;
   d.stage_core_bytes = sb.ok ? sb.core_bytes : 0;
   d.so_term_ptr = sb.off_term_ptr;
   d.so_term_rxn = sb.off_term_rxn;

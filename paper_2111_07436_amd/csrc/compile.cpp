@@ -597,7 +597,7 @@ std::string compile_mechanism(const camp_reaction* rxns, int n_rxn, const camp_s
 StageBlock build_stage_block(const Compiled& C) {
   StageBlock sb;
   const int N = C.n_state, Z = C.nnz, R = C.n_rxn;
-  if (N >= 1023 || Z > 65535 || (long long)C.lu_pa.size() >= (1 << 20)) return sb;
+  if (N >= 1023 || Z > 65535) return sb;
   std::vector<uint8_t>& b = sb.bytes;
   auto put = [&](const void* src, size_t n) {
     size_t off = (b.size() + 15) / 16 * 16;
@@ -616,53 +616,62 @@ StageBlock build_stage_block(const Compiled& C) {
     rx[k] = v;
   }
   sb.off_rx = put(rx.data(), 4 * rx.size());
-  std::vector<uint16_t> col(C.col.begin(), C.col.end()), rp(C.row_ptr.begin(), C.row_ptr.end()),
-      dg(C.diag.begin(), C.diag.end());
-  sb.off_col = put(col.data(), 2 * col.size());
-  sb.off_rowptr = put(rp.data(), 2 * rp.size());
+  std::vector<uint16_t> dg(C.diag.begin(), C.diag.end());
   sb.off_diag = put(dg.data(), 2 * dg.size());
-  // solve rows per level, longest rows first inside a level
-  auto rows_by_level = [&](const std::vector<Task>& tasks, const std::vector<int>& lptr,
-                           std::vector<uint16_t>& rows, std::vector<uint16_t>& lp) {
-    lp.assign(lptr.size(), 0);
+  // triangular solves: the product terms of each level (levels without terms dropped)
+  auto solve_terms = [&](const std::vector<Task>& tasks, const std::vector<int>& lptr,
+                         const std::vector<int>& pa, const std::vector<int>& pb, int& off,
+                         int& off_lp, int& n_lev) {
+    std::vector<uint32_t> t, lp(1, 0);
     for (size_t l = 0; l + 1 < lptr.size(); ++l) {
-      std::vector<Task> t(tasks.begin() + lptr[l], tasks.begin() + lptr[l + 1]);
-      std::stable_sort(t.begin(), t.end(), [](const Task& a, const Task& c) {
-        return (a.pend - a.pbeg) > (c.pend - c.pbeg);
-      });
-      for (auto& x : t) rows.push_back((uint16_t)x.dst);
-      lp[l + 1] = (uint16_t)rows.size();
+      const size_t before = t.size();
+      for (int i = lptr[l]; i < lptr[l + 1]; ++i)
+        for (int q = tasks[i].pbeg; q < tasks[i].pend; ++q) {
+          t.push_back((uint32_t)tasks[i].dst | ((uint32_t)pb[q] << 16));
+          t.push_back((uint32_t)pa[q]);
+        }
+      if (t.size() > before) lp.push_back((uint32_t)(t.size() / 2));
     }
+    n_lev = (int)lp.size() - 1;
+    off = put(t.data(), 4 * t.size());
+    off_lp = put(lp.data(), 4 * lp.size());
   };
-  std::vector<uint16_t> fr, flp, br, blp;
-  rows_by_level(C.fwd_tasks, C.fwd_level_ptr, fr, flp);
-  rows_by_level(C.bwd_tasks, C.bwd_level_ptr, br, blp);
-  sb.off_fwd_rows = put(fr.data(), 2 * fr.size());
-  sb.off_fwd_lptr = put(flp.data(), 2 * flp.size());
-  sb.off_bwd_rows = put(br.data(), 2 * br.size());
-  sb.off_bwd_lptr = put(blp.data(), 2 * blp.size());
-  // LU tasks: x = dst | diag << 16 (0xFFFF: none), y = pbeg | count << 20; pairs pa | pb << 16
-  std::vector<uint32_t> tk, pr;
-  std::vector<uint32_t> llp(C.lu_level_ptr.size(), 0);
-  for (size_t l = 0; l + 1 < C.lu_level_ptr.size(); ++l) {
-    std::vector<Task> t(C.lu_tasks.begin() + C.lu_level_ptr[l], C.lu_tasks.begin() + C.lu_level_ptr[l + 1]);
-    std::stable_sort(t.begin(), t.end(), [](const Task& a, const Task& c) {
-      return (a.pend - a.pbeg) > (c.pend - c.pbeg);
-    });
-    for (auto& x : t) {
-      const int cnt = x.pend - x.pbeg;
-      if (cnt >= 4096) return StageBlock{};
-      tk.push_back((uint32_t)x.dst | ((uint32_t)(x.diag < 0 ? 0xFFFF : x.diag) << 16));
-      tk.push_back((uint32_t)pr.size() | ((uint32_t)cnt << 20));
-      for (int q = x.pbeg; q < x.pend; ++q)
-        pr.push_back((uint32_t)C.lu_pa[q] | ((uint32_t)C.lu_pb[q] << 16));
+  solve_terms(C.fwd_tasks, C.fwd_level_ptr, C.fwd_pa, C.fwd_pb, sb.off_sf, sb.off_sf_lp, sb.n_sf_lev);
+  solve_terms(C.bwd_tasks, C.bwd_level_ptr, C.bwd_pa, C.bwd_pb, sb.off_sb, sb.off_sb_lp, sb.n_sb_lev);
+  // LU: product terms and finalize entries per level
+  std::vector<char> is_diag(Z, 0), touched(Z, 0);
+  for (int t = 0; t < N; ++t) is_diag[C.diag[t]] = 1;
+  for (const Task& x : C.lu_tasks) touched[x.dst] = 1;
+  std::vector<uint32_t> lt, ltp(1, 0), lf, lfp(1, 0);
+  for (int t = 0; t < N; ++t)
+    if (!touched[C.diag[t]]) lf.push_back((uint32_t)C.diag[t] | (0xFFFFu << 16));
+  lfp.push_back((uint32_t)lf.size());
+  for (int l = 0; l < C.lu_levels(); ++l) {
+    for (int i = C.lu_level_ptr[l]; i < C.lu_level_ptr[l + 1]; ++i) {
+      const Task& x = C.lu_tasks[i];
+      for (int q = x.pbeg; q < x.pend; ++q) {
+        lt.push_back((uint32_t)x.dst | ((uint32_t)C.lu_pa[q] << 16));
+        lt.push_back((uint32_t)C.lu_pb[q]);
+      }
+      if (x.diag >= 0)
+        lf.push_back((uint32_t)x.dst | ((uint32_t)x.diag << 16));
+      else if (is_diag[x.dst])
+        lf.push_back((uint32_t)x.dst | (0xFFFFu << 16));
     }
-    llp[l + 1] = (uint32_t)(tk.size() / 2);
+    ltp.push_back((uint32_t)(lt.size() / 2));
+    lfp.push_back((uint32_t)lf.size());
   }
-  sb.n_lu_tk = (int)(tk.size() / 2);
-  sb.off_lu_tk = put(tk.data(), 4 * tk.size());
-  sb.off_lu_pr = put(pr.data(), 4 * pr.size());
-  sb.off_lu_lptr = put(llp.data(), 4 * llp.size());
+  sb.off_lt = put(lt.data(), 4 * lt.size());
+  sb.off_lt_lp = put(ltp.data(), 4 * ltp.size());
+  sb.off_lf = put(lf.data(), 4 * lf.size());
+  sb.off_lf_lp = put(lfp.data(), 4 * lfp.size());
+  // row scaling of the strict upper factor
+  std::vector<uint32_t> us;
+  for (int t = 0; t < N; ++t)
+    for (int q = C.diag[t] + 1; q < C.row_ptr[t + 1]; ++q)
+      us.push_back((uint32_t)q | ((uint32_t)C.diag[t] << 16));
+  sb.n_us = (int)us.size();
+  sb.off_us = put(us.data(), 4 * us.size());
   b.resize((b.size() + 15) / 16 * 16);
   sb.core_bytes = (int)b.size();
   // extension: forcing terms and Jacobian contributions

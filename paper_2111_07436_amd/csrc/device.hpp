@@ -51,8 +51,8 @@ struct DevMech {
   const uint8_t* stage;
   int stage_bytes;        // whole block
   int stage_core_bytes;   // core prefix (index tables of the sparse steps)
-  int so_rx, so_col, so_rowptr, so_diag, so_fwd_rows, so_fwd_lptr, so_bwd_rows, so_bwd_lptr;
-  int so_lu_tk, so_lu_pr, so_lu_lptr;
+  int so_rx, so_diag, so_sf, so_sf_lp, so_sb, so_sb_lp, so_lt, so_lt_lp, so_lf, so_lf_lp, so_us;
+  int n_sf_lev, n_sb_lev, n_us;
   int so_term_ptr, so_term_rxn, so_term_coef, so_jc_ptr, so_jc_part, so_jc_coef, so_is_diag;
 };
 
@@ -143,24 +143,50 @@ __device__ inline double rate_constant(const DevMech& m, int r, double T, double
   return kc * p0 * kAtmPa / (kGasConstant * T * n_abs);
 }
 
-// Sum over the 64 lanes of a wavefront; every lane receives the same value.
+// Moves a double between lanes with one DPP pattern (both 32-bit halves).
+template <int kCtrl>
+__device__ __forceinline__ double dpp_move(double v) {
+  const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_mov_dpp((int)(unsigned)b, kCtrl, 0xF, 0xF, false);
+  const unsigned hi = (unsigned)__builtin_amdgcn_mov_dpp((int)(unsigned)(b >> 32), kCtrl, 0xF, 0xF, false);
+  return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+
+// The value of `v` held by lane `l` (a compile-time constant), as a wavefront-uniform value.
+template <int l>
+__device__ __forceinline__ double lane_value(double v) {
+  const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)b, l);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), l);
+  return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+
+// DPP patterns inside each row of 16 lanes.
+constexpr int kDppQuadXor1 = 0xB1;       // quad_perm [1,0,3,2]
+constexpr int kDppQuadXor2 = 0x4E;       // quad_perm [2,3,0,1]
+constexpr int kDppRowHalfMirror = 0x141; // lane i <-> 7 - i within 8 lanes
+constexpr int kDppRowMirror = 0x140;     // lane i <-> 15 - i within 16 lanes
+
+// Sum over the 64 lanes of a wavefront, the same value in every lane. All 64 lanes must
+// be active. Row sums by DPP moves, then the four row sums in a fixed order.
 __device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, kWave);
-  return v;
+  v += dpp_move<kDppQuadXor1>(v);
+  v += dpp_move<kDppQuadXor2>(v);
+  v += dpp_move<kDppRowHalfMirror>(v);
+  v += dpp_move<kDppRowMirror>(v);
+  return (lane_value<0>(v) + lane_value<16>(v)) + (lane_value<32>(v) + lane_value<48>(v));
 }
 
 __device__ __forceinline__ double wave_max(double v) {
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) v = fmax(v, __shfl_xor(v, o, kWave));
-  return v;
+  v = fmax(v, dpp_move<kDppQuadXor1>(v));
+  v = fmax(v, dpp_move<kDppQuadXor2>(v));
+  v = fmax(v, dpp_move<kDppRowHalfMirror>(v));
+  v = fmax(v, dpp_move<kDppRowMirror>(v));
+  return fmax(fmax(lane_value<0>(v), lane_value<16>(v)), fmax(lane_value<32>(v), lane_value<48>(v)));
 }
 
-__device__ __forceinline__ int wave_or(int v) {
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) v |= __shfl_xor(v, o, kWave);
-  return v;
-}
+// Nonzero in any active lane.
+__device__ __forceinline__ int wave_or(int v) { return __ballot(v != 0) != 0ull; }
 
 // Cell-interleaved slab addressing: element x (of X per cell) of cell c lives at
 // ((c / 64) * X + x) * 64 + c % 64, so the 64 lanes of a wavefront touching the same x of

@@ -32,6 +32,14 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Wavefront-uniform copy of a value every lane holds.
+__device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// LDS accumulation: several lanes of one instruction may target the same entry.
+__device__ __forceinline__ void lds_add(double* p, double v) {
+  __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+}
+
 // Accessors of the compact table block: the core tables through `b`, the forcing-term and
 // Jacobian-contribution extension through `e`; each base is LDS (staged) or global memory.
 struct Tabs {
@@ -46,16 +54,16 @@ struct Tabs {
   __device__ double jc_coef(int q) const { return reinterpret_cast<const double*>(e + m.so_jc_coef)[q]; }
   __device__ bool is_diag(int s) const { return reinterpret_cast<const uint8_t*>(e + m.so_is_diag)[s] != 0; }
   __device__ uint32_t rx(int k) const { return reinterpret_cast<const uint32_t*>(b + m.so_rx)[k]; }
-  __device__ int col(int q) const { return reinterpret_cast<const uint16_t*>(b + m.so_col)[q]; }
-  __device__ int rowptr(int t) const { return reinterpret_cast<const uint16_t*>(b + m.so_rowptr)[t]; }
   __device__ int dg(int t) const { return reinterpret_cast<const uint16_t*>(b + m.so_diag)[t]; }
-  __device__ int fwd_row(int i) const { return reinterpret_cast<const uint16_t*>(b + m.so_fwd_rows)[i]; }
-  __device__ int fwd_lp(int l) const { return reinterpret_cast<const uint16_t*>(b + m.so_fwd_lptr)[l]; }
-  __device__ int bwd_row(int i) const { return reinterpret_cast<const uint16_t*>(b + m.so_bwd_rows)[i]; }
-  __device__ int bwd_lp(int l) const { return reinterpret_cast<const uint16_t*>(b + m.so_bwd_lptr)[l]; }
-  __device__ uint2 lu_tk(int i) const { return reinterpret_cast<const uint2*>(b + m.so_lu_tk)[i]; }
-  __device__ uint32_t lu_pr(int q) const { return reinterpret_cast<const uint32_t*>(b + m.so_lu_pr)[q]; }
-  __device__ int lu_lp(int l) const { return (int)reinterpret_cast<const uint32_t*>(b + m.so_lu_lptr)[l]; }
+  __device__ uint2 sf(int i) const { return reinterpret_cast<const uint2*>(b + m.so_sf)[i]; }
+  __device__ int sf_lp(int l) const { return (int)reinterpret_cast<const uint32_t*>(b + m.so_sf_lp)[l]; }
+  __device__ uint2 sb(int i) const { return reinterpret_cast<const uint2*>(b + m.so_sb)[i]; }
+  __device__ int sb_lp(int l) const { return (int)reinterpret_cast<const uint32_t*>(b + m.so_sb_lp)[l]; }
+  __device__ uint2 lt(int i) const { return reinterpret_cast<const uint2*>(b + m.so_lt)[i]; }
+  __device__ int lt_lp(int l) const { return (int)reinterpret_cast<const uint32_t*>(b + m.so_lt_lp)[l]; }
+  __device__ uint32_t lf(int i) const { return reinterpret_cast<const uint32_t*>(b + m.so_lf)[i]; }
+  __device__ int lf_lp(int l) const { return (int)reinterpret_cast<const uint32_t*>(b + m.so_lf_lp)[l]; }
+  __device__ uint32_t us(int i) const { return reinterpret_cast<const uint32_t*>(b + m.so_us)[i]; }
 };
 
 template <int NPL>
@@ -130,31 +138,48 @@ struct WaveCell {
     wave_sync();
   }
 
-  // In-place Crout LU of M, one dependency level at a time. Returns 0 if a pivot is not a
-  // finite nonzero.
+  // In-place Crout LU of M, one dependency level at a time: the level's product terms in
+  // parallel (one per lane), then its finalize entries (L entries times the reciprocal
+  // pivot, pivots inverted). Leaves the unit-diagonal factors: L strictly below the
+  // diagonal, reciprocal pivots on it, and U / diag(U) strictly above. Returns 0 if a
+  // pivot is not a finite nonzero.
   __device__ int lu() const {
+    int flo = uniform(tb.lf_lp(0));
+    int fhi = uniform(tb.lf_lp(1));
+    for (int i = flo + lane; i < fhi; i += kWave) {
+      const int d = tb.lf(i) & 0xFFFF;
+      M[d] = 1.0 / M[d];
+    }
+    wave_sync();
+    int tlo = uniform(tb.lt_lp(0));
     for (int l = 0; l < m.lu_levels; ++l) {
-      const int lo = tb.lu_lp(l), hi = tb.lu_lp(l + 1);
-      for (int i = lo + lane; i < hi; i += kWave) {
-        const uint2 t = tb.lu_tk(i);
-        const int dst = t.x & 0xFFFF, dgs = t.x >> 16;
-        const int pb = t.y & 0xFFFFF, cnt = t.y >> 20;
-        double acc = M[dst];
-#pragma unroll 4
-        for (int q = 0; q < cnt; ++q) {
-          const uint32_t pr = tb.lu_pr(pb + q);
-          acc -= M[pr & 0xFFFF] * M[pr >> 16];
-        }
-        if (dgs != 0xFFFF) acc /= M[dgs];
-        M[dst] = acc;
+      const int thi = uniform(tb.lt_lp(l + 1));
+      flo = fhi;
+      fhi = uniform(tb.lf_lp(l + 2));
+      for (int i = tlo + lane; i < thi; i += kWave) {
+        const uint2 e = tb.lt(i);
+        lds_add(&M[e.x & 0xFFFF], -(M[e.x >> 16] * M[e.y]));
+      }
+      tlo = thi;
+      wave_sync();
+      if (flo == fhi) continue;
+      for (int i = flo + lane; i < fhi; i += kWave) {
+        const uint32_t e = tb.lf(i);
+        const int dst = e & 0xFFFF, pv = e >> 16;
+        M[dst] = pv == 0xFFFF ? 1.0 / M[dst] : M[dst] * M[pv];
       }
       wave_sync();
     }
+    for (int i = lane; i < m.n_us; i += kWave) {
+      const uint32_t e = tb.us(i);
+      M[e & 0xFFFF] *= M[e >> 16];
+    }
     int bad = 0;
     for (int t = lane; t < m.N; t += kWave) {
-      const double u = M[tb.dg(t)];
-      if (!(fabs(u) > 0.0) || !isfinite(u)) bad = 1;
+      const double r = M[tb.dg(t)];
+      if (!(fabs(r) > 0.0) || !isfinite(r)) bad = 1;
     }
+    wave_sync();
     return !wave_or(bad);
   }
 
@@ -163,30 +188,50 @@ struct WaveCell {
     return lu();
   }
 
-  // xl <- (LU)^-1 xl: forward then backward substitution over the CSR rows, level by level.
+  // Conversions between the factor form lu() leaves and the conventional one (unit L
+  // strictly below the diagonal, U on and above it).
+  __device__ void factors_to_conventional() const {
+    for (int i = lane; i < m.n_us; i += kWave) {
+      const uint32_t e = tb.us(i);
+      M[e & 0xFFFF] /= M[e >> 16];
+    }
+    wave_sync();
+    for (int t = lane; t < m.N; t += kWave) M[tb.dg(t)] = 1.0 / M[tb.dg(t)];
+    wave_sync();
+  }
+  __device__ void factors_from_conventional() const {
+    for (int t = lane; t < m.N; t += kWave) M[tb.dg(t)] = 1.0 / M[tb.dg(t)];
+    wave_sync();
+    for (int i = lane; i < m.n_us; i += kWave) {
+      const uint32_t e = tb.us(i);
+      M[e & 0xFFFF] *= M[e >> 16];
+    }
+    wave_sync();
+  }
+
+  // xl <- (LU)^-1 xl from the factors lu() leaves: forward sweep, diagonal scaling,
+  // backward sweep; each sweep a level at a time with its product terms in parallel.
   __device__ void solve() const {
-    for (int l = 0; l < m.fwd_levels; ++l) {
-      const int lo = tb.fwd_lp(l), hi = tb.fwd_lp(l + 1);
+    int lo = uniform(tb.sf_lp(0));
+    for (int l = 0; l < m.n_sf_lev; ++l) {
+      const int hi = uniform(tb.sf_lp(l + 1));
       for (int i = lo + lane; i < hi; i += kWave) {
-        const int t = tb.fwd_row(i);
-        double acc = xl[t];
-        const int q1 = tb.dg(t);
-#pragma unroll 4
-        for (int q = tb.rowptr(t); q < q1; ++q) acc -= M[q] * xl[tb.col(q)];
-        xl[t] = acc;
+        const uint2 e = tb.sf(i);
+        lds_add(&xl[e.x & 0xFFFF], -(M[e.y] * xl[e.x >> 16]));
       }
+      lo = hi;
       wave_sync();
     }
-    for (int l = 0; l < m.bwd_levels; ++l) {
-      const int lo = tb.bwd_lp(l), hi = tb.bwd_lp(l + 1);
+    for (int t = lane; t < m.N; t += kWave) xl[t] *= M[tb.dg(t)];
+    wave_sync();
+    lo = uniform(tb.sb_lp(0));
+    for (int l = 0; l < m.n_sb_lev; ++l) {
+      const int hi = uniform(tb.sb_lp(l + 1));
       for (int i = lo + lane; i < hi; i += kWave) {
-        const int t = tb.bwd_row(i);
-        double acc = xl[t];
-        const int d = tb.dg(t), q1 = tb.rowptr(t + 1);
-#pragma unroll 4
-        for (int q = d + 1; q < q1; ++q) acc -= M[q] * xl[tb.col(q)];
-        xl[t] = acc / M[d];
+        const uint2 e = tb.sb(i);
+        lds_add(&xl[e.x & 0xFFFF], -(M[e.y] * xl[e.x >> 16]));
       }
+      lo = hi;
       wave_sync();
     }
   }
@@ -582,7 +627,6 @@ __device__ __forceinline__ Tabs stage_tables(const DevMech& m, double* lds) {
 
 }  // namespace
 
-constexpr int kMaxWavesPerWG = 8;
 // Up to 3 species per lane the kernel fits 256 VGPRs (two wavefronts per SIMD, workgroups
 // of up to 8 wavefronts); larger states get 512 VGPRs (workgroups of up to 4 wavefronts).
 template <int NPL>
@@ -610,7 +654,7 @@ __global__ __launch_bounds__(kWave * max_waves_per_wg<NPL>()) void bdf_wave_kern
   while (true) {
     int cell = 0;
     if (lane == 0) cell = atomicAdd(queue, 1);
-    cell = __shfl(cell, 0, kWave);
+    cell = uniform(cell);
     if (cell >= n_cells) break;
     solve_one_cell<NPL>(m, env, state, cell, sp, status, stats, Wc);
   }
@@ -711,11 +755,13 @@ __global__ __launch_bounds__(kWave) void wave_step_kernel(DevMech m, int op, int
     for (int s = lane; s < m.Z; s += kWave) W.M[s] = out[(size_t)cell * m.Z + s];
     wave_sync();
     W.lu();
+    W.factors_to_conventional();
     for (int s = lane; s < m.Z; s += kWave) out[(size_t)cell * m.Z + s] = W.M[s];
   } else {                   // solve: kin = LU, out = b -> x
     for (int s = lane; s < m.Z; s += kWave) W.M[s] = kin[(size_t)cell * m.Z + s];
     for (int t = lane; t < m.N; t += kWave) W.xl[t] = out[(size_t)cell * m.N + m.perm[t]];
     wave_sync();
+    W.factors_from_conventional();
     W.solve();
     for (int t = lane; t < m.N; t += kWave) out[(size_t)cell * m.N + m.perm[t]] = W.xl[t];
   }

@@ -90,22 +90,37 @@ struct Compiled {
   int bwd_levels() const { return (int)bwd_level_ptr.size() - 1; }
 };
 
-// Compact copies of the latency-critical tables (reactant indices, CSR pattern with
-// level-ordered solve rows, Crout LU tasks and pairs) in one byte block, laid out so a
-// workgroup can copy it into LDS with 16-byte loads. 16-bit indices: requires N < 1023
-// (10-bit reactant fields) and Z <= 65535.
+// Compact copies of the tables the wavefront engine reads at every step, in one byte block
+// laid out so a workgroup can copy it into LDS with 16-byte loads. 16-bit indices: requires
+// N < 1023 (10-bit reactant fields) and Z <= 65535.
+//
+// The sparse LU and triangular solves are stored as term lists, level by level: every
+// term is one product subtracted from one entry, so all terms of a level run in parallel.
+//   LU level l:  M[dst] -= M[pa] * M[pb] for its terms; then its finalize entries:
+//                M[dst] *= M[piv] for L entries (M[piv] holds the pivot's reciprocal),
+//                M[dst] = 1 / M[dst] for pivots. Finalize segment 0 (before level 0)
+//                inverts the pivots no elimination step touches. After the last level the
+//                strict upper entries of each row are scaled by that row's reciprocal
+//                pivot, so both triangular factors have a unit diagonal.
+//   forward:     x[dst] -= M[slot] * x[src] (unit lower)
+//   diagonal:    x[t] *= M[diag[t]]
+//   backward:    x[dst] -= M[slot] * x[src] (row-scaled upper, unit diagonal)
+// Layout: rx u32 [R]; diag u16 [N]; sf/sb terms uint2 {dst | src << 16, slot} with level
+// pointers u32; LU terms uint2 {dst | pa << 16, pb} with level pointers u32 [levels + 1];
+// finalize u32 {dst | piv << 16} (piv 0xFFFF: invert) with pointers u32 [levels + 2];
+// row scaling u32 {slot | piv << 16}.
 // The block has a core part (the above) followed by an extension with the forcing terms
 // and Jacobian contributions (term_ptr/jc_ptr u32, rxn/partial u16, coef f64, is_diag u8),
 // so a workgroup may stage only the core when the whole block does not fit.
 struct StageBlock {
   std::vector<uint8_t> bytes;
   int core_bytes = 0;
-  int off_rx = 0, off_col = 0, off_rowptr = 0, off_diag = 0;
-  int off_fwd_rows = 0, off_fwd_lptr = 0, off_bwd_rows = 0, off_bwd_lptr = 0;
-  int off_lu_tk = 0, off_lu_pr = 0, off_lu_lptr = 0;
+  int off_rx = 0, off_diag = 0;
+  int off_sf = 0, off_sf_lp = 0, off_sb = 0, off_sb_lp = 0;
+  int off_lt = 0, off_lt_lp = 0, off_lf = 0, off_lf_lp = 0, off_us = 0;
+  int n_sf_lev = 0, n_sb_lev = 0, n_us = 0;
   int off_term_ptr = 0, off_term_rxn = 0, off_term_coef = 0;
   int off_jc_ptr = 0, off_jc_part = 0, off_jc_coef = 0, off_is_diag = 0;
-  int n_lu_tk = 0;
   bool ok = false;   // false when the mechanism exceeds the 16-bit index ranges
 };
 
