@@ -143,13 +143,12 @@ int upload(camp_mech* mh, int device, DeviceTables& out) {
   d.n_sb_lev = sb.n_sb_lev;
   d.n_us = sb.n_us;
   d.stage_core_bytes = sb.ok ? sb.core_bytes : 0;
-  d.so_term_ptr = sb.off_term_ptr;
-  d.so_term_rxn = sb.off_term_rxn;
-  d.so_term_coef = sb.off_term_coef;
-  d.so_jc_ptr = sb.off_jc_ptr;
-  d.so_jc_part = sb.off_jc_part;
-  d.so_jc_coef = sb.off_jc_coef;
-  d.so_is_diag = sb.off_is_diag;
+  d.so_ft = sb.off_ft;
+  d.so_ft_coef = sb.off_ft_coef;
+  d.so_jt = sb.off_jt;
+  d.so_jt_coef = sb.off_jt_coef;
+  d.n_ft = sb.n_ft;
+  d.n_jt = sb.n_jt;
   out.device = device;
   out.blob = blob;
   out.bytes = total;

@@ -594,6 +594,32 @@ std::string compile_mechanism(const camp_reaction* rxns, int n_rxn, const camp_s
   return "";
 }
 
+// Reorders (dst, payload) items so that consecutive items go to different destinations
+// where possible: the first item of every destination, then the second, and so on. Items
+// of one level run one per lane, and lanes of one instruction that accumulate into the
+// same entry are serialized by the LDS.
+template <class T>
+static std::vector<std::pair<int, T>> interleave_by_dst(const std::vector<std::pair<int, T>>& in) {
+  std::vector<int> order;
+  std::vector<std::vector<T>> groups;
+  std::vector<int> where;
+  for (auto& e : in) {
+    if ((int)where.size() <= e.first) where.resize(e.first + 1, -1);
+    if (where[e.first] < 0) {
+      where[e.first] = (int)groups.size();
+      groups.emplace_back();
+      order.push_back(e.first);
+    }
+    groups[where[e.first]].push_back(e.second);
+  }
+  std::vector<std::pair<int, T>> out;
+  out.reserve(in.size());
+  for (size_t k = 0; out.size() < in.size(); ++k)
+    for (size_t g = 0; g < groups.size(); ++g)
+      if (k < groups[g].size()) out.push_back({order[g], groups[g][k]});
+  return out;
+}
+
 StageBlock build_stage_block(const Compiled& C) {
   StageBlock sb;
   const int N = C.n_state, Z = C.nnz, R = C.n_rxn;
@@ -624,13 +650,15 @@ StageBlock build_stage_block(const Compiled& C) {
                          int& off_lp, int& n_lev) {
     std::vector<uint32_t> t, lp(1, 0);
     for (size_t l = 0; l + 1 < lptr.size(); ++l) {
-      const size_t before = t.size();
+      std::vector<std::pair<int, int>> lv;
       for (int i = lptr[l]; i < lptr[l + 1]; ++i)
-        for (int q = tasks[i].pbeg; q < tasks[i].pend; ++q) {
-          t.push_back((uint32_t)tasks[i].dst | ((uint32_t)pb[q] << 16));
-          t.push_back((uint32_t)pa[q]);
-        }
-      if (t.size() > before) lp.push_back((uint32_t)(t.size() / 2));
+        for (int q = tasks[i].pbeg; q < tasks[i].pend; ++q) lv.push_back({tasks[i].dst, q});
+      if (lv.empty()) continue;
+      for (auto& e : interleave_by_dst(lv)) {
+        t.push_back((uint32_t)e.first | ((uint32_t)pb[e.second] << 16));
+        t.push_back((uint32_t)pa[e.second]);
+      }
+      lp.push_back((uint32_t)(t.size() / 2));
     }
     n_lev = (int)lp.size() - 1;
     off = put(t.data(), 4 * t.size());
@@ -647,12 +675,17 @@ StageBlock build_stage_block(const Compiled& C) {
     if (!touched[C.diag[t]]) lf.push_back((uint32_t)C.diag[t] | (0xFFFFu << 16));
   lfp.push_back((uint32_t)lf.size());
   for (int l = 0; l < C.lu_levels(); ++l) {
+    std::vector<std::pair<int, int>> lv;
     for (int i = C.lu_level_ptr[l]; i < C.lu_level_ptr[l + 1]; ++i) {
       const Task& x = C.lu_tasks[i];
-      for (int q = x.pbeg; q < x.pend; ++q) {
-        lt.push_back((uint32_t)x.dst | ((uint32_t)C.lu_pa[q] << 16));
-        lt.push_back((uint32_t)C.lu_pb[q]);
-      }
+      for (int q = x.pbeg; q < x.pend; ++q) lv.push_back({x.dst, q});
+    }
+    for (auto& e : interleave_by_dst(lv)) {
+      lt.push_back((uint32_t)e.first | ((uint32_t)C.lu_pa[e.second] << 16));
+      lt.push_back((uint32_t)C.lu_pb[e.second]);
+    }
+    for (int i = C.lu_level_ptr[l]; i < C.lu_level_ptr[l + 1]; ++i) {
+      const Task& x = C.lu_tasks[i];
       if (x.diag >= 0)
         lf.push_back((uint32_t)x.dst | ((uint32_t)x.diag << 16));
       else if (is_diag[x.dst])
@@ -674,19 +707,34 @@ StageBlock build_stage_block(const Compiled& C) {
   sb.off_us = put(us.data(), 4 * us.size());
   b.resize((b.size() + 15) / 16 * 16);
   sb.core_bytes = (int)b.size();
-  // extension: forcing terms and Jacobian contributions
+  // extension: forcing terms and Jacobian contributions as flat term lists
   if (C.n_partials >= 65536 || R >= 65536) return StageBlock{};
-  std::vector<uint32_t> tp(C.term_ptr.begin(), C.term_ptr.end()), jp(C.jc_ptr.begin(), C.jc_ptr.end());
-  std::vector<uint16_t> trx(C.term_rxn.begin(), C.term_rxn.end()), jpart(C.jc_part.begin(), C.jc_part.end());
-  std::vector<uint8_t> isd(Z, 0);
-  for (int t = 0; t < N; ++t) isd[C.diag[t]] = 1;
-  sb.off_term_coef = put(C.term_coef.data(), 8 * C.term_coef.size());
-  sb.off_jc_coef = put(C.jc_coef.data(), 8 * C.jc_coef.size());
-  sb.off_term_ptr = put(tp.data(), 4 * tp.size());
-  sb.off_jc_ptr = put(jp.data(), 4 * jp.size());
-  sb.off_term_rxn = put(trx.data(), 2 * trx.size());
-  sb.off_jc_part = put(jpart.data(), 2 * jpart.size());
-  sb.off_is_diag = put(isd.data(), isd.size());
+  std::vector<std::pair<int, uint32_t>> ft, jt;
+  std::vector<int> ft_src, jt_src;
+  for (int t = 0; t < N; ++t)
+    for (int q = C.term_ptr[t]; q < C.term_ptr[t + 1]; ++q)
+      ft.push_back({t, (uint32_t)q});
+  for (int z = 0; z < Z; ++z)
+    for (int q = C.jc_ptr[z]; q < C.jc_ptr[z + 1]; ++q)
+      jt.push_back({z, (uint32_t)q});
+  ft = interleave_by_dst(ft);
+  jt = interleave_by_dst(jt);
+  std::vector<uint32_t> fi, ji;
+  std::vector<double> fc, jcf;
+  for (auto& e : ft) {
+    fi.push_back((uint32_t)e.first | ((uint32_t)C.term_rxn[e.second] << 16));
+    fc.push_back(C.term_coef[e.second]);
+  }
+  for (auto& e : jt) {
+    ji.push_back((uint32_t)e.first | ((uint32_t)C.jc_part[e.second] << 16));
+    jcf.push_back(C.jc_coef[e.second]);
+  }
+  sb.n_ft = (int)fi.size();
+  sb.n_jt = (int)ji.size();
+  sb.off_ft_coef = put(fc.data(), 8 * fc.size());
+  sb.off_jt_coef = put(jcf.data(), 8 * jcf.size());
+  sb.off_ft = put(fi.data(), 4 * fi.size());
+  sb.off_jt = put(ji.data(), 4 * ji.size());
   b.resize((b.size() + 15) / 16 * 16);
   sb.ok = true;
   return sb;

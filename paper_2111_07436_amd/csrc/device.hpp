@@ -53,7 +53,7 @@ struct DevMech {
   int stage_core_bytes;   // core prefix (index tables of the sparse steps)
   int so_rx, so_diag, so_sf, so_sf_lp, so_sb, so_sb_lp, so_lt, so_lt_lp, so_lf, so_lf_lp, so_us;
   int n_sf_lev, n_sb_lev, n_us;
-  int so_term_ptr, so_term_rxn, so_term_coef, so_jc_ptr, so_jc_part, so_jc_coef, so_is_diag;
+  int so_ft, so_ft_coef, so_jt, so_jt_coef, n_ft, n_jt;
 };
 
 // Per-cell environment (device pointers, row-major [cells] / [cells][n_inst]).

@@ -40,19 +40,64 @@ __device__ __forceinline__ void lds_add(double* p, double v) {
   __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
 }
 
+// One update of a term loop: add `v` to entry `dst`.
+struct TermUpdate {
+  int dst;
+  double v;
+};
+
+// Runs the terms i = lo + lane, lo + lane + 64, ... < hi of a term list in groups of kU:
+// the loads of a group (gather) are all issued before any of its updates (scatter), so
+// their latencies overlap. Only valid where no term of the list reads what another writes.
+template <int kU, class Gather, class Scatter>
+__device__ __forceinline__ void for_terms(int lo, int hi, int lane, Gather gather, Scatter scatter) {
+  int i = lo + lane;
+  for (; i + (kU - 1) * kWave < hi; i += kU * kWave) {
+    TermUpdate it[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) it[u] = gather(i + u * kWave);
+#pragma unroll
+    for (int u = 0; u < kU; ++u) scatter(it[u]);
+  }
+  for (; i < hi; i += kWave) scatter(gather(i));
+}
+
+constexpr int kTermBatch = 4;
+
+// Level pointers of a term list held in registers: lane k holds entry k and entry k + 64,
+// so reading the bounds of a level is a lane read instead of an LDS round trip. Lists of
+// more than 127 levels read the rest from the table.
+struct LevelPtrs {
+  int a, b;
+};
+
+// Loads entries 0..nlev of a level-pointer table (ptr(l) reads entry l); entry 0 is 0.
+template <class Ptr>
+__device__ __forceinline__ LevelPtrs load_levels(int nlev, Ptr ptr) {
+  const int lane = threadIdx.x % kWave;
+  LevelPtrs p{0, 0};
+  if (lane <= nlev) p.a = ptr(lane);
+  if (lane + kWave <= nlev) p.b = ptr(lane + kWave);
+  return p;
+}
+
+template <class Ptr>
+__device__ __forceinline__ int level_ptr(const LevelPtrs& p, int l, Ptr ptr) {
+  if (l < kWave) return __builtin_amdgcn_readlane(p.a, l);
+  if (l < 2 * kWave) return __builtin_amdgcn_readlane(p.b, l - kWave);
+  return uniform(ptr(l));
+}
+
 // Accessors of the compact table block: the core tables through `b`, the forcing-term and
 // Jacobian-contribution extension through `e`; each base is LDS (staged) or global memory.
 struct Tabs {
   const char* b;
   const char* e;
   const DevMech& m;
-  __device__ int term_ptr(int t) const { return (int)reinterpret_cast<const uint32_t*>(e + m.so_term_ptr)[t]; }
-  __device__ int term_rxn(int q) const { return reinterpret_cast<const uint16_t*>(e + m.so_term_rxn)[q]; }
-  __device__ double term_coef(int q) const { return reinterpret_cast<const double*>(e + m.so_term_coef)[q]; }
-  __device__ int jc_ptr(int s) const { return (int)reinterpret_cast<const uint32_t*>(e + m.so_jc_ptr)[s]; }
-  __device__ int jc_part(int q) const { return reinterpret_cast<const uint16_t*>(e + m.so_jc_part)[q]; }
-  __device__ double jc_coef(int q) const { return reinterpret_cast<const double*>(e + m.so_jc_coef)[q]; }
-  __device__ bool is_diag(int s) const { return reinterpret_cast<const uint8_t*>(e + m.so_is_diag)[s] != 0; }
+  __device__ uint32_t ft(int i) const { return reinterpret_cast<const uint32_t*>(e + m.so_ft)[i]; }
+  __device__ double ft_coef(int i) const { return reinterpret_cast<const double*>(e + m.so_ft_coef)[i]; }
+  __device__ uint32_t jt(int i) const { return reinterpret_cast<const uint32_t*>(e + m.so_jt)[i]; }
+  __device__ double jt_coef(int i) const { return reinterpret_cast<const double*>(e + m.so_jt_coef)[i]; }
   __device__ uint32_t rx(int k) const { return reinterpret_cast<const uint32_t*>(b + m.so_rx)[k]; }
   __device__ int dg(int t) const { return reinterpret_cast<const uint16_t*>(b + m.so_diag)[t]; }
   __device__ uint2 sf(int i) const { return reinterpret_cast<const uint2*>(b + m.so_sf)[i]; }
@@ -88,7 +133,9 @@ struct WaveCell {
     return sqrt(wave_sum(s) / m.N);
   }
 
-  // P[k] = r_k from yl; then f for owned species. yl must be visible to all lanes.
+  // P[k] = r_k from yl; then f for owned species, accumulated term by term (one term per
+  // lane) in xl, which no caller holds live across this call. yl must be visible to all
+  // lanes.
   __device__ void forcing(double (&f)[NPL]) const {
     for (int k = lane; k < m.R; k += kWave) {
       const uint32_t v = tb.rx(k);
@@ -99,22 +146,26 @@ struct WaveCell {
       if (c != 0x3FF) r *= yl[c];
       P[k] = r;
     }
+    for (int t = lane; t < m.N; t += kWave) xl[t] = 0.0;
+    wave_sync();
+    for_terms<kTermBatch>(
+        0, m.n_ft, lane,
+        [&](int i) {
+          const uint32_t e = tb.ft(i);
+          return TermUpdate{(int)(e & 0xFFFF), tb.ft_coef(i) * P[e >> 16]};
+        },
+        [&](const TermUpdate& u) { lds_add(&xl[u.dst], u.v); });
     wave_sync();
 #pragma unroll
     for (int i = 0; i < NPL; ++i) {
       const int t = lane + kWave * i;
-      double acc = 0.0;
-      if (t < m.N) {
-        const int q0 = tb.term_ptr(t), q1 = tb.term_ptr(t + 1);
-#pragma unroll 4
-        for (int q = q0; q < q1; ++q) acc += tb.term_coef(q) * P[tb.term_rxn(q)];
-      }
-      f[i] = acc;
+      f[i] = t < m.N ? xl[t] : 0.0;
     }
     wave_sync();
   }
 
-  // M = I - c J(yl) in the filled pattern (fill slots 0 off the diagonal).
+  // M = I - c J(yl) in the filled pattern (fill slots 0 off the diagonal), accumulated
+  // contribution by contribution (one per lane).
   __device__ void newton_matrix(double c) const {
     for (int k = lane; k < m.R; k += kWave) {
       const uint32_t v = tb.rx(k);
@@ -127,14 +178,18 @@ struct WaveCell {
       if (b != 0x3FF) P[base + 1] = kk * ya * yc;
       if (cc != 0x3FF) P[base + 2] = kk * ya * yb;
     }
+    for (int s = lane; s < m.Z; s += kWave) M[s] = 0.0;
     wave_sync();
-    for (int s = lane; s < m.Z; s += kWave) {
-      double acc = 0.0;
-      const int q0 = tb.jc_ptr(s), q1 = tb.jc_ptr(s + 1);
-#pragma unroll 4
-      for (int q = q0; q < q1; ++q) acc += tb.jc_coef(q) * P[tb.jc_part(q)];
-      M[s] = (tb.is_diag(s) ? 1.0 : 0.0) - c * acc;
-    }
+    const double mc = -c;
+    for_terms<kTermBatch>(
+        0, m.n_jt, lane,
+        [&](int i) {
+          const uint32_t e = tb.jt(i);
+          return TermUpdate{(int)(e & 0xFFFF), mc * tb.jt_coef(i) * P[e >> 16]};
+        },
+        [&](const TermUpdate& u) { lds_add(&M[u.dst], u.v); });
+    wave_sync();
+    for (int t = lane; t < m.N; t += kWave) M[tb.dg(t)] += 1.0;
     wave_sync();
   }
 
@@ -144,24 +199,26 @@ struct WaveCell {
   // diagonal, reciprocal pivots on it, and U / diag(U) strictly above. Returns 0 if a
   // pivot is not a finite nonzero.
   __device__ int lu() const {
-    int flo = uniform(tb.lf_lp(0));
-    int fhi = uniform(tb.lf_lp(1));
-    for (int i = flo + lane; i < fhi; i += kWave) {
+    const int L = m.lu_levels;
+    const LevelPtrs tp = load_levels(L, [&](int l) { return tb.lt_lp(l); });
+    const LevelPtrs fp = load_levels(L + 1, [&](int l) { return tb.lf_lp(l); });
+    int fhi = level_ptr(fp, 1, [&](int l) { return tb.lf_lp(l); });
+    for (int i = lane; i < fhi; i += kWave) {
       const int d = tb.lf(i) & 0xFFFF;
       M[d] = 1.0 / M[d];
     }
     wave_sync();
-    int tlo = uniform(tb.lt_lp(0));
-    for (int l = 0; l < m.lu_levels; ++l) {
-      const int thi = uniform(tb.lt_lp(l + 1));
-      flo = fhi;
-      fhi = uniform(tb.lf_lp(l + 2));
+    int tlo = 0;
+    for (int l = 0; l < L; ++l) {
+      const int thi = level_ptr(tp, l + 1, [&](int k) { return tb.lt_lp(k); });
       for (int i = tlo + lane; i < thi; i += kWave) {
         const uint2 e = tb.lt(i);
         lds_add(&M[e.x & 0xFFFF], -(M[e.x >> 16] * M[e.y]));
       }
       tlo = thi;
       wave_sync();
+      const int flo = fhi;
+      fhi = level_ptr(fp, l + 2, [&](int k) { return tb.lf_lp(k); });
       if (flo == fhi) continue;
       for (int i = flo + lane; i < fhi; i += kWave) {
         const uint32_t e = tb.lf(i);
@@ -209,31 +266,32 @@ struct WaveCell {
     wave_sync();
   }
 
-  // xl <- (LU)^-1 xl from the factors lu() leaves: forward sweep, diagonal scaling,
-  // backward sweep; each sweep a level at a time with its product terms in parallel.
-  __device__ void solve() const {
-    int lo = uniform(tb.sf_lp(0));
-    for (int l = 0; l < m.n_sf_lev; ++l) {
-      const int hi = uniform(tb.sf_lp(l + 1));
+  // One triangular sweep over the unit-diagonal factor: x[dst] -= M[slot] * x[src] for
+  // the terms of each level, one term per lane.
+  template <bool kForward>
+  __device__ void sweep() const {
+    const int nlev = kForward ? m.n_sf_lev : m.n_sb_lev;
+    auto lp = [&](int l) { return kForward ? tb.sf_lp(l) : tb.sb_lp(l); };
+    const LevelPtrs p = load_levels(nlev, lp);
+    int lo = 0;
+    for (int l = 0; l < nlev; ++l) {
+      const int hi = level_ptr(p, l + 1, lp);
       for (int i = lo + lane; i < hi; i += kWave) {
-        const uint2 e = tb.sf(i);
+        const uint2 e = kForward ? tb.sf(i) : tb.sb(i);
         lds_add(&xl[e.x & 0xFFFF], -(M[e.y] * xl[e.x >> 16]));
       }
       lo = hi;
       wave_sync();
     }
+  }
+
+  // xl <- (LU)^-1 xl from the factors lu() leaves: forward sweep, diagonal scaling,
+  // backward sweep.
+  __device__ void solve() const {
+    sweep<true>();
     for (int t = lane; t < m.N; t += kWave) xl[t] *= M[tb.dg(t)];
     wave_sync();
-    lo = uniform(tb.sb_lp(0));
-    for (int l = 0; l < m.n_sb_lev; ++l) {
-      const int hi = uniform(tb.sb_lp(l + 1));
-      for (int i = lo + lane; i < hi; i += kWave) {
-        const uint2 e = tb.sb(i);
-        lds_add(&xl[e.x & 0xFFFF], -(M[e.y] * xl[e.x >> 16]));
-      }
-      lo = hi;
-      wave_sync();
-    }
+    sweep<false>();
   }
 };
 

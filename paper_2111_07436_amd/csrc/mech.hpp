@@ -110,8 +110,10 @@ struct Compiled {
 // finalize u32 {dst | piv << 16} (piv 0xFFFF: invert) with pointers u32 [levels + 2];
 // row scaling u32 {slot | piv << 16}.
 // The block has a core part (the above) followed by an extension with the forcing terms
-// and Jacobian contributions (term_ptr/jc_ptr u32, rxn/partial u16, coef f64, is_diag u8),
-// so a workgroup may stage only the core when the whole block does not fit.
+// (u32 {species | reaction << 16}, coef f64) and the Jacobian contributions
+// (u32 {slot | partial << 16}, coef f64) as flat lists, so a workgroup may stage only the
+// core when the whole block does not fit. Terms of every list are interleaved by
+// destination (see interleave_by_dst).
 struct StageBlock {
   std::vector<uint8_t> bytes;
   int core_bytes = 0;
@@ -119,8 +121,7 @@ struct StageBlock {
   int off_sf = 0, off_sf_lp = 0, off_sb = 0, off_sb_lp = 0;
   int off_lt = 0, off_lt_lp = 0, off_lf = 0, off_lf_lp = 0, off_us = 0;
   int n_sf_lev = 0, n_sb_lev = 0, n_us = 0;
-  int off_term_ptr = 0, off_term_rxn = 0, off_term_coef = 0;
-  int off_jc_ptr = 0, off_jc_part = 0, off_jc_coef = 0, off_is_diag = 0;
+  int off_ft = 0, off_ft_coef = 0, off_jt = 0, off_jt_coef = 0, n_ft = 0, n_jt = 0;
   bool ok = false;   // false when the mechanism exceeds the 16-bit index ranges
 };
 
