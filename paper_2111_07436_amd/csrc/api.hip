@@ -248,34 +248,39 @@ int solve_device_tuned(camp_mech* mh, const DevMech& dm, int n_cells, double* d_
       return CAMP_EINVAL;
     }
     const int waves = std::max(1, tu.waves);
-    const int stage = std::max(0, std::min(2, tu.stage));
+    const int stage = std::max(0, std::min(3, tu.stage));
     if (wave_wg_lds_bytes(dm, waves, stage) > kLdsBytes) {
       set_error("mechanism does not fit the wavefront engine's LDS budget");
       return CAMP_EINVAL;
     }
     const int wg_total = (n_cells + waves - 1) / waves;
-    if (tu.persistent) {
-      int* queue = nullptr;
-      e = hipMallocAsync((void**)&queue, 256, stream);
+    if (tu.persistent || stage == 3) {
+      // queue counter, then (mode 3) the rate-constant scratch of every resident wavefront
+      const int grid = std::max(1, std::min(wg_total, n_cus() * std::max(1, tu.grid_mult)));
+      const size_t kc_bytes = stage == 3 ? sizeof(double) * (size_t)grid * waves * dm.R : 0;
+      char* buf = nullptr;
+      e = hipMallocAsync((void**)&buf, 256 + kc_bytes, stream);
       if (e != hipSuccess) return hip_fail(e, "hipMallocAsync(queue)");
+      int* queue = reinterpret_cast<int*>(buf);
+      double* kc = stage == 3 ? reinterpret_cast<double*>(buf + 256) : nullptr;
       e = launch_fill_int(queue, 1, 0, stream);
-      const int grid = std::max(1, std::min(wg_total, n_cus() * tu.grid_mult));
       if (e == hipSuccess)
-        e = launch_bdf_wave(dm, env, d_state, n_cells, sp, d_status, d_stats, queue, grid, waves,
-                            stage, stream);
-      hipError_t e2 = hipFreeAsync(queue, stream);
+        e = launch_bdf_wave(dm, env, d_state, n_cells, sp, d_status, d_stats, queue, kc, grid,
+                            waves, stage, stream);
+      hipError_t e2 = hipFreeAsync(buf, stream);
       if (e == hipSuccess) e = e2;
     } else {
-      e = launch_bdf_wave(dm, env, d_state, n_cells, sp, d_status, d_stats, nullptr, wg_total,
-                          waves, stage, stream);
+      e = launch_bdf_wave(dm, env, d_state, n_cells, sp, d_status, d_stats, nullptr, nullptr,
+                          wg_total, waves, stage, stream);
     }
   }
   if (e != hipSuccess) return hip_fail(e, "solve launch");
   return CAMP_OK;
 }
 
-// Occupancy-driven default: the largest number of wavefronts per workgroup (<= 8) such that
-// the workgroups resident on one CU hold the most cells, preferring the most tables staged.
+// Occupancy-driven default: the launch mode and wavefronts per workgroup (<= 8) such that
+// the workgroups resident on one CU hold the most cells, preferring the most tables staged
+// and rate constants in LDS (mode 3 only when it fits more cells).
 Tuning default_tuning(const DevMech& dm, int n_cells) {
   Tuning t;
   const bool fits_wave = (dm.N + kWave - 1) / kWave <= 9 && dm.stage &&
@@ -285,7 +290,7 @@ Tuning default_tuning(const DevMech& dm, int n_cells) {
   int best_cells = 0;
   const int wmax = wave_max_waves(dm.N);   // also the resident wavefronts per CU by VGPRs
   t.stage = -1;
-  for (int stage = 2; stage >= 0; --stage)
+  for (int stage : {2, 1, 0, 3})
     for (int w = 1; w <= wmax; ++w) {
       const size_t b = wave_wg_lds_bytes(dm, w, stage);
       if (b > kLdsBytes) break;
@@ -405,7 +410,7 @@ int camp_solve_device(camp_mech* mh, int n_cells, double* d_state, const camp_en
     if (opts->persistent >= 0) tu.persistent = opts->persistent ? 1 : 0;
     if (opts->wg_per_cu > 0) tu.grid_mult = opts->wg_per_cu;
     if (opts->waves_per_wg > 0) tu.waves = std::min(opts->waves_per_wg, 8);
-    if (opts->stage_tables >= 0) tu.stage = std::min(opts->stage_tables, 2);
+    if (opts->stage_tables >= 0) tu.stage = std::min(opts->stage_tables, 3);
   }
   return solve_device_tuned(mh, *dm, n_cells, d_state, d_env, sp, opts, d_status, d_stats,
                             (hipStream_t)stream, tu);

@@ -3,11 +3,11 @@
 // On the first call for a bucket it times short trials of each candidate on a copy of the
 // call's own first cells (the caller's arrays are never written by a trial) and caches
 // the fastest. Candidates: the wavefront engine at the two deepest LDS table-staging levels
-// that fit, 1..8
+// that fit (and with rate constants in global scratch when that fits more cells), 1..8
 // cells per workgroup, a persistent grid sized to the resident capacity or one workgroup
-// per cell batch; and the lane-per-cell fused engine. With CAMP_TUNE_CACHE set to a file
-// path, choices persist across processes (keyed by a hash of the compiled mechanism, the
-// device name and the bucket).
+// per cell batch; the lane-per-cell fused engine only when no wavefront launch fits. With
+// CAMP_TUNE_CACHE set to a file path, choices persist across processes (keyed by a hash of
+// the compiled mechanism, the device name and the bucket).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -109,12 +109,16 @@ std::vector<Tuning> candidates(const DevMech& dm) {
     const int wmax = wave_max_waves(dm.N);
     for (int w : {1, 2, 4, 8}) {
       if (w > wmax) continue;
-      int tried = 0;   // the two most-staged levels that fit
-      for (int stage = 2; stage >= 0 && tried < 2; --stage) {
+      int tried = 0;   // the two most-staged modes that fit, then mode 3 if it holds more cells
+      int best_wgs = 0;
+      for (int stage : {2, 1, 0, 3}) {
         const size_t b = wave_wg_lds_bytes(dm, w, stage);
         if (b > kLdsBytes) continue;
-        ++tried;
         const int wgs = (int)(kLdsBytes / b);   // resident workgroups per CU by LDS
+        if (stage == 3 ? std::min(wgs * w, wmax) <= std::min(best_wgs * w, wmax) : tried >= 2)
+          continue;
+        if (stage != 3) ++tried;
+        best_wgs = std::max(best_wgs, wgs);
         Tuning t;
         t.engine = CAMP_ENGINE_FUSED_WAVE;
         t.waves = w;
@@ -122,7 +126,7 @@ std::vector<Tuning> candidates(const DevMech& dm) {
         t.persistent = 1;
         t.grid_mult = std::max(1, std::min(wgs, std::max(1, wmax / w)));
         out.push_back(t);
-        if (w == 1 || w == 8) {
+        if ((w == 1 || w == 8) && stage != 3) {
           Tuning np = t;
           np.persistent = 0;
           out.push_back(np);
@@ -130,9 +134,8 @@ std::vector<Tuning> candidates(const DevMech& dm) {
       }
     }
   }
-  // The lane-per-cell engine only competes when LDS holds at most two cells per CU.
-  const size_t cell = wave_wg_lds_bytes(dm, 1, 0);
-  if (!wave_ok || cell == 0 || kLdsBytes / cell <= 2) {
+  // The lane-per-cell engine (matrix in HBM) only when no wavefront launch fits.
+  if (out.empty()) {
     Tuning lane;
     lane.engine = CAMP_ENGINE_FUSED_LANE;
     out.push_back(lane);

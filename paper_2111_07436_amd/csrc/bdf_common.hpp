@@ -31,6 +31,12 @@ constexpr double kRestartFactor = 0.1;
 // the step cut by this factor. Without it, undershoots of fast species drive the
 // bimolecular terms unstable and the step size collapses.
 constexpr double kConstraintFactor = 0.25;
+// Attempts per cell: 0 Newton with Jacobian reuse; 1 full Newton; 2 full Newton with the
+// absolute tolerance tightened by kRetryAtolFactor (a cell whose tiny, atol-controlled
+// species undershoot into the constraint over and over integrates at a tolerance at least
+// as tight as requested). A cell that fails an attempt (statuses 1-4) goes to the next.
+constexpr int kAttempts = 3;
+constexpr double kRetryAtolFactor = 0.01;
 
 enum CellStatus : int { ST_OK = 0, ST_MAX_STEPS = 1, ST_H_MIN = 2, ST_ERR_FAIL = 3,
                         ST_NEWTON_FAIL = 4, ST_NONFINITE = 5 };

@@ -181,17 +181,23 @@ __device__ inline double lane_wrms_d_w(const Lane& L, double scale) {
 
 // ---------------------------------------------------------------- phase functions
 
+// Absolute tolerance of the slot's current attempt.
+__device__ inline double slot_atol(const LaneCtx& C, int slot) {
+  return C.st.full[slot] >= 2 ? C.sp.atol * kRetryAtolFactor : C.sp.atol;
+}
+
 // Rate constants, initial state, starting step. Leaves the slot in PH_IDLE (ready to
-// predict) or PH_DONE (failed). full: integrate with full Newton (a retry keeps the
-// counters of the first attempt).
-__device__ void lane_init(const LaneCtx& C, int slot, int cell, int full) {
+// predict) or PH_DONE (failed). attempt (see kAttempts): 0 Newton with Jacobian reuse,
+// 1 full Newton, 2 full Newton with a tighter atol; a retry keeps the counters of the
+// earlier attempts.
+__device__ void lane_init(const LaneCtx& C, int slot, int cell, int attempt, bool retry) {
   const Lane L(C, slot);
   const DevMech& m = C.m;
   const LaneState& S = C.st;
   S.cell[slot] = cell;
-  S.full[slot] = full;
+  S.full[slot] = attempt;
   camp_cell_stats cs = {0, 0, 0, 0, 0, 0, 0, 1};
-  if (full && !C.sp.full_newton) cs = S.st[slot];
+  if (retry) cs = S.st[slot];
   const double Tk = C.env.T[cell], Pp = C.env.P[cell];
   const double cz = C.env.cos_sza ? C.env.cos_sza[cell] : 1.0;
   const double* rad = C.env.radius ? C.env.radius + (size_t)cell * m.n_inst : nullptr;
@@ -220,7 +226,7 @@ __device__ void lane_init(const LaneCtx& C, int slot, int cell, int full) {
     const double span = C.sp.dt;
     double s0 = 0.0, s1 = 0.0;
     for (int t = 0; t < m.N; ++t) {
-      const double sc = C.sp.atol + C.sp.rtol * fabs(L.D(0, t));
+      const double sc = slot_atol(C, slot) + C.sp.rtol * fabs(L.D(0, t));
       const double wt = sc > 0.0 ? 1.0 / sc : 0.0;
       L.w(t) = wt;
       L.x(t) = L.f(t);   // keep f0
@@ -280,7 +286,7 @@ __device__ void lane_predict(const LaneCtx& C, int slot, int new_step) {
     }
     int ok = 1;
     for (int i = 0; i < m.N; ++i) {
-      const double wt = 1.0 / (C.sp.rtol * fabs(L.D(0, i)) + C.sp.atol);
+      const double wt = 1.0 / (C.sp.rtol * fabs(L.D(0, i)) + slot_atol(C, slot));
       L.w(i) = wt;
       if (!isfinite(wt)) ok = 0;
     }
@@ -549,16 +555,15 @@ __device__ inline void lane_store_stats(const LaneCtx& C, int slot) {
 
 __device__ inline bool retry_status(int s) { return s >= ST_MAX_STEPS && s <= ST_NEWTON_FAIL; }
 
-// retry == 0: start every cell; retry == 1: restart with full Newton only the cells whose
-// first integration failed (the others stay done).
-__global__ __launch_bounds__(256) void plain_init_kernel(LaneCtx C, int retry) {
+// First attempt: start every cell; later attempts restart only the cells whose previous
+// attempt failed (the others stay done).
+__global__ __launch_bounds__(256) void plain_init_kernel(LaneCtx C, int attempt) {
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= C.n_cells) return;
-  if (retry) {
-    if (!retry_status(C.status[c])) return;
-  }
+  const bool retry = attempt > C.sp.full_newton;
+  if (retry && !retry_status(C.status[c])) return;
   C.status[c] = -1;
-  lane_init(C, c, c, retry ? 1 : C.sp.full_newton);
+  lane_init(C, c, c, attempt, retry);
   C.st.it[c] = 1;   // "new step" flag for the first predict
 }
 
@@ -611,9 +616,9 @@ __global__ __launch_bounds__(256) void fused_lane_kernel(LaneCtx C, int n_slots,
   while (true) {
     const int cell = atomicAdd(queue, 1);
     if (cell >= C.n_cells) break;
-    for (int full = C.sp.full_newton; full < 2; ++full) {
+    for (int attempt = C.sp.full_newton; attempt < kAttempts; ++attempt) {
       C.status[cell] = -1;
-      lane_init(C, slot, cell, full);
+      lane_init(C, slot, cell, attempt, attempt > C.sp.full_newton);
       int new_step = 1;
       while (C.st.phase[slot] != PH_DONE) {
         lane_predict(C, slot, new_step);
@@ -773,11 +778,11 @@ hipError_t run_plain(const DevMech& m, const DevEnv& env, double* state, int n_c
       return e;
     }
   }
-  // Pass 0 integrates every cell; pass 1 restarts with full Newton the cells whose first
-  // integration failed. Each chunk runs kChunk step attempts for every active cell; a pass
-  // stops when no cell is active.
+  // The first pass integrates every cell; each later pass restarts the cells whose previous
+  // attempt failed (full Newton, then also a tighter atol). Each chunk runs kChunk step
+  // attempts for every active cell; a pass stops when no cell is active.
   const long long max_chunks = (long long)sp.max_steps / kChunk + 2;
-  for (int pass = sp.full_newton ? 1 : 0; pass < 2 && e == hipSuccess; ++pass) {
+  for (int pass = sp.full_newton ? 1 : 0; pass < kAttempts && e == hipSuccess; ++pass) {
     hipLaunchKernelGGL(plain_init_kernel, grid, block, 0, stream, C, pass);
     for (long long ch = 0; ch < max_chunks; ++ch) {
       if (exec) {

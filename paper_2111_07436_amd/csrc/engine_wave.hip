@@ -113,6 +113,9 @@ struct Tabs {
 
 template <int NPL>
 struct WaveCell {
+  // Terms per lane issued together in the LU and sweep levels: levels of large mechanisms
+  // hold several terms per lane, small ones rarely more than one.
+  static constexpr int kLevelBatch = NPL >= 4 ? 4 : 1;
   const DevMech& m;
   Tabs tb;
   double* M;
@@ -211,10 +214,13 @@ struct WaveCell {
     int tlo = 0;
     for (int l = 0; l < L; ++l) {
       const int thi = level_ptr(tp, l + 1, [&](int k) { return tb.lt_lp(k); });
-      for (int i = tlo + lane; i < thi; i += kWave) {
-        const uint2 e = tb.lt(i);
-        lds_add(&M[e.x & 0xFFFF], -(M[e.x >> 16] * M[e.y]));
-      }
+      for_terms<kLevelBatch>(
+          tlo, thi, lane,
+          [&](int i) {
+            const uint2 e = tb.lt(i);
+            return TermUpdate{(int)(e.x & 0xFFFF), M[e.x >> 16] * M[e.y]};
+          },
+          [&](const TermUpdate& u) { lds_add(&M[u.dst], -u.v); });
       tlo = thi;
       wave_sync();
       const int flo = fhi;
@@ -276,10 +282,13 @@ struct WaveCell {
     int lo = 0;
     for (int l = 0; l < nlev; ++l) {
       const int hi = level_ptr(p, l + 1, lp);
-      for (int i = lo + lane; i < hi; i += kWave) {
-        const uint2 e = kForward ? tb.sf(i) : tb.sb(i);
-        lds_add(&xl[e.x & 0xFFFF], -(M[e.y] * xl[e.x >> 16]));
-      }
+      for_terms<kLevelBatch>(
+          lo, hi, lane,
+          [&](int i) {
+            const uint2 e = kForward ? tb.sf(i) : tb.sb(i);
+            return TermUpdate{(int)(e.x & 0xFFFF), M[e.y] * xl[e.x >> 16]};
+          },
+          [&](const TermUpdate& u) { lds_add(&xl[u.dst], -u.v); });
       lo = hi;
       wave_sync();
     }
@@ -625,9 +634,9 @@ __device__ __forceinline__ int integrate(const DevMech& m, double* yrow, const S
   return status;
 }
 
-// Rate constants, then the integration; a cell whose Newton-with-reuse integration fails
-// (too many steps, step below the minimum, repeated error-test or Newton failures) is
-// integrated again from its input with full Newton.
+// Rate constants, then the integration; a cell whose integration fails (too many steps,
+// step below the minimum, repeated error-test or Newton failures) is integrated again from
+// its input: with full Newton, then with full Newton and a tighter absolute tolerance.
 template <int NPL>
 __device__ void solve_one_cell(const DevMech& m, const DevEnv& env, double* state, int cell,
                                const SolveParams& sp, int* status_out, camp_cell_stats* stats_out,
@@ -645,10 +654,13 @@ __device__ void solve_one_cell(const DevMech& m, const DevEnv& env, double* stat
     W.kc[k] = v;
     if (!isfinite(v)) bad = 1;
   }
+  __threadfence_block();   // rate constants (LDS or global scratch) visible to all lanes
   double* yrow = state + (size_t)cell * m.N;
   int status = ST_OK;
-  for (int full = sp.full_newton ? 1 : 0; full < 2; ++full) {
-    status = integrate<NPL>(m, yrow, sp, bad, full, cs, W);
+  for (int attempt = sp.full_newton ? 1 : 0; attempt < kAttempts; ++attempt) {
+    SolveParams spa = sp;
+    if (attempt == 2) spa.atol *= kRetryAtolFactor;
+    status = integrate<NPL>(m, yrow, spa, bad, attempt > 0, cs, W);
     if (status < ST_MAX_STEPS || status > ST_NEWTON_FAIL) break;
   }
   if (lane == 0) {
@@ -658,22 +670,30 @@ __device__ void solve_one_cell(const DevMech& m, const DevEnv& env, double* stat
   wave_sync();
 }
 
-__device__ inline size_t cell_doubles(const DevMech& m) {
+// Launch modes of the wavefront engine (table staging and where rate constants live):
+//   0  tables read from global memory, rate constants in LDS
+//   1  core index tables staged in LDS
+//   2  whole table block staged in LDS
+//   3  tables from global memory and rate constants in a global per-wavefront scratch
+//      (persistent launches only), for mechanisms whose per-cell LDS is the occupancy limit
+constexpr int kModeKcGlobal = 3;
+
+// LDS doubles of one cell: M, y, x, partials/rates, and the rate constants unless mode 3.
+__host__ __device__ inline size_t cell_doubles(const DevMech& m, int mode) {
   const int np = m.n_part > m.R ? m.n_part : m.R;
-  return (size_t)m.Z + 2 * (size_t)m.N + np + m.R;
+  return (size_t)m.Z + 2 * (size_t)m.N + np + (mode == kModeKcGlobal ? 0 : m.R);
 }
 
-// Bytes of the table block staged in LDS at staging level `stage`: 0 none, 1 the core
-// index tables, 2 the whole block (core + forcing terms + Jacobian contributions).
-__host__ __device__ inline int staged_bytes(const DevMech& m, int stage) {
-  return stage == 2 ? m.stage_bytes : stage == 1 ? m.stage_core_bytes : 0;
+// Bytes of the table block staged in LDS in launch mode `mode`.
+__host__ __device__ inline int staged_bytes(const DevMech& m, int mode) {
+  return mode == 2 ? m.stage_bytes : mode == 1 ? m.stage_core_bytes : 0;
 }
 
 // Copies the staged part of the table block into LDS (16-byte units).
 template <int kStage>
 __device__ __forceinline__ Tabs stage_tables(const DevMech& m, double* lds) {
   const char* g = reinterpret_cast<const char*>(m.stage);
-  if (kStage == 0) return Tabs{g, g, m};
+  if (kStage == 0 || kStage == kModeKcGlobal) return Tabs{g, g, m};
   const uint4* src = reinterpret_cast<const uint4*>(m.stage);
   uint4* dst = reinterpret_cast<uint4*>(lds);
   const int n16 = staged_bytes(m, kStage) / 16;
@@ -692,18 +712,20 @@ constexpr int max_waves_per_wg() { return NPL <= 3 ? 8 : 4; }
 int wave_max_waves(int n_state) { return (n_state + kWave - 1) / kWave <= 3 ? 8 : 4; }
 
 // blockDim.x = 64 * W: W wavefronts, one cell each. queue != nullptr: persistent grid
-// pulling cells from the counter; else cell = blockIdx.x * W + wavefront.
+// pulling cells from the counter; else cell = blockIdx.x * W + wavefront. Mode 3 keeps the
+// rate constants at kc_glob + (blockIdx.x * W + wavefront) * R and needs the queue.
 template <int NPL, int kStage>
 __global__ __launch_bounds__(kWave * max_waves_per_wg<NPL>()) void bdf_wave_kernel(
     DevMech m, DevEnv env, double* state, int n_cells, SolveParams sp, int* status,
-    camp_cell_stats* stats, int* queue) {
+    camp_cell_stats* stats, int* queue, double* kc_glob) {
   extern __shared__ double lds[];
   const Tabs tab = stage_tables<kStage>(m, lds);
   const int W = blockDim.x / kWave, wid = threadIdx.x / kWave, lane = threadIdx.x % kWave;
-  double* base = lds + staged_bytes(m, kStage) / 8 + wid * cell_doubles(m);
+  double* base = lds + staged_bytes(m, kStage) / 8 + wid * cell_doubles(m, kStage);
   const int np = m.n_part > m.R ? m.n_part : m.R;
-  const WaveCell<NPL> Wc{m, tab, base, base + m.Z, base + m.Z + m.N,
-                         base + m.Z + 2 * m.N, base + m.Z + 2 * m.N + np, lane};
+  double* kc = kStage == kModeKcGlobal ? kc_glob + (size_t)(blockIdx.x * W + wid) * m.R
+                                       : base + m.Z + 2 * m.N + np;
+  const WaveCell<NPL> Wc{m, tab, base, base + m.Z, base + m.Z + m.N, base + m.Z + 2 * m.N, kc, lane};
   if (!queue) {
     const int cell = blockIdx.x * W + wid;
     if (cell < n_cells) solve_one_cell<NPL>(m, env, state, cell, sp, status, stats, Wc);
@@ -718,60 +740,59 @@ __global__ __launch_bounds__(kWave * max_waves_per_wg<NPL>()) void bdf_wave_kern
   }
 }
 
-size_t wave_cell_bytes(const DevMech& m) {
-  const int np = m.n_part > m.R ? m.n_part : m.R;
-  return sizeof(double) * ((size_t)m.Z + 2 * (size_t)m.N + np + m.R);
-}
+size_t wave_cell_bytes(const DevMech& m) { return sizeof(double) * cell_doubles(m, 0); }
 
 size_t wave_lds_bytes(const DevMech& m) { return wave_cell_bytes(m); }
 
-// LDS bytes of a workgroup of `waves` cells at table staging level `stage` (0, 1, 2).
-size_t wave_wg_lds_bytes(const DevMech& m, int waves, int stage) {
-  return (size_t)staged_bytes(m, stage) + (size_t)waves * wave_cell_bytes(m);
+// LDS bytes of a workgroup of `waves` cells in launch mode `mode` (0..3).
+size_t wave_wg_lds_bytes(const DevMech& m, int waves, int mode) {
+  return (size_t)staged_bytes(m, mode) + (size_t)waves * sizeof(double) * cell_doubles(m, mode);
 }
 
 template <int NPL, int kStage>
 hipError_t launch_wave_npl(const DevMech& m, const DevEnv& env, double* state, int n_cells,
                            const SolveParams& sp, int* status, camp_cell_stats* stats, int* queue,
-                           int grid, int waves, size_t lds, hipStream_t stream) {
+                           double* kc_glob, int grid, int waves, size_t lds, hipStream_t stream) {
   hipError_t e = hipFuncSetAttribute((const void*)bdf_wave_kernel<NPL, kStage>,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL((bdf_wave_kernel<NPL, kStage>), dim3(grid), dim3(kWave * waves), lds, stream,
-                     m, env, state, n_cells, sp, status, stats, queue);
+                     m, env, state, n_cells, sp, status, stats, queue, kc_glob);
   return hipGetLastError();
 }
 
 template <int NPL>
 hipError_t launch_wave_stage(const DevMech& m, const DevEnv& env, double* state, int n_cells,
                              const SolveParams& sp, int* status, camp_cell_stats* stats,
-                             int* queue, int grid, int waves, int stage, size_t lds,
-                             hipStream_t stream) {
+                             int* queue, double* kc_glob, int grid, int waves, int stage,
+                             size_t lds, hipStream_t stream) {
   switch (stage) {
-    case 0: return launch_wave_npl<NPL, 0>(m, env, state, n_cells, sp, status, stats, queue, grid, waves, lds, stream);
-    case 1: return launch_wave_npl<NPL, 1>(m, env, state, n_cells, sp, status, stats, queue, grid, waves, lds, stream);
-    case 2: return launch_wave_npl<NPL, 2>(m, env, state, n_cells, sp, status, stats, queue, grid, waves, lds, stream);
+    case 0: return launch_wave_npl<NPL, 0>(m, env, state, n_cells, sp, status, stats, queue, kc_glob, grid, waves, lds, stream);
+    case 1: return launch_wave_npl<NPL, 1>(m, env, state, n_cells, sp, status, stats, queue, kc_glob, grid, waves, lds, stream);
+    case 2: return launch_wave_npl<NPL, 2>(m, env, state, n_cells, sp, status, stats, queue, kc_glob, grid, waves, lds, stream);
+    case 3: return launch_wave_npl<NPL, 3>(m, env, state, n_cells, sp, status, stats, queue, kc_glob, grid, waves, lds, stream);
     default: return hipErrorInvalidValue;
   }
 }
 
 hipError_t launch_bdf_wave(const DevMech& m, const DevEnv& env, double* state, int n_cells,
                            const SolveParams& sp, int* status, camp_cell_stats* stats, int* queue,
-                           int grid, int waves, int stage, hipStream_t stream) {
+                           double* kc_glob, int grid, int waves, int stage, hipStream_t stream) {
   const size_t lds = wave_wg_lds_bytes(m, waves, stage);
   const int npl = (m.N + kWave - 1) / kWave;
   if (waves < 1 || waves > wave_max_waves(m.N)) return hipErrorInvalidValue;
-  if (stage < 0 || stage > 2 || !m.stage) return hipErrorInvalidValue;
+  if (stage < 0 || stage > 3 || !m.stage) return hipErrorInvalidValue;
+  if (stage == kModeKcGlobal && (!queue || !kc_glob)) return hipErrorInvalidValue;
   switch (npl) {
-    case 1: return launch_wave_stage<1>(m, env, state, n_cells, sp, status, stats, queue, grid, waves, stage, lds, stream);
-    case 2: return launch_wave_stage<2>(m, env, state, n_cells, sp, status, stats, queue, grid, waves, stage, lds, stream);
-    case 3: return launch_wave_stage<3>(m, env, state, n_cells, sp, status, stats, queue, grid, waves, stage, lds, stream);
-    case 4: return launch_wave_stage<4>(m, env, state, n_cells, sp, status, stats, queue, grid, waves, stage, lds, stream);
-    case 5: return launch_wave_stage<5>(m, env, state, n_cells, sp, status, stats, queue, grid, waves, stage, lds, stream);
-    case 6: return launch_wave_stage<6>(m, env, state, n_cells, sp, status, stats, queue, grid, waves, stage, lds, stream);
-    case 7: return launch_wave_stage<7>(m, env, state, n_cells, sp, status, stats, queue, grid, waves, stage, lds, stream);
-    case 8: return launch_wave_stage<8>(m, env, state, n_cells, sp, status, stats, queue, grid, waves, stage, lds, stream);
-    case 9: return launch_wave_stage<9>(m, env, state, n_cells, sp, status, stats, queue, grid, waves, stage, lds, stream);
+    case 1: return launch_wave_stage<1>(m, env, state, n_cells, sp, status, stats, queue, kc_glob, grid, waves, stage, lds, stream);
+    case 2: return launch_wave_stage<2>(m, env, state, n_cells, sp, status, stats, queue, kc_glob, grid, waves, stage, lds, stream);
+    case 3: return launch_wave_stage<3>(m, env, state, n_cells, sp, status, stats, queue, kc_glob, grid, waves, stage, lds, stream);
+    case 4: return launch_wave_stage<4>(m, env, state, n_cells, sp, status, stats, queue, kc_glob, grid, waves, stage, lds, stream);
+    case 5: return launch_wave_stage<5>(m, env, state, n_cells, sp, status, stats, queue, kc_glob, grid, waves, stage, lds, stream);
+    case 6: return launch_wave_stage<6>(m, env, state, n_cells, sp, status, stats, queue, kc_glob, grid, waves, stage, lds, stream);
+    case 7: return launch_wave_stage<7>(m, env, state, n_cells, sp, status, stats, queue, kc_glob, grid, waves, stage, lds, stream);
+    case 8: return launch_wave_stage<8>(m, env, state, n_cells, sp, status, stats, queue, kc_glob, grid, waves, stage, lds, stream);
+    case 9: return launch_wave_stage<9>(m, env, state, n_cells, sp, status, stats, queue, kc_glob, grid, waves, stage, lds, stream);
     default: return hipErrorInvalidValue;
   }
 }

@@ -22,7 +22,8 @@ struct Tuning {
   int persistent = 1;        // wave engine: 1 = queue-driven persistent grid
   int grid_mult = 8;         // wave engine: workgroups per CU when persistent
   int waves = 1;             // wave engine: wavefronts (cells) per workgroup
-  int stage = 1;             // wave engine: tables staged in LDS (0 none, 1 index, 2 all)
+  int stage = 1;             // wave engine launch mode: tables staged in LDS (0 none, 1 index,
+                             // 2 all) or 3 (none; rate constants in global scratch)
   double ms = 0.0;           // measured trial time
 };
 
@@ -43,7 +44,7 @@ size_t wave_wg_lds_bytes(const DevMech& m, int waves, int stage);
 int wave_max_waves(int n_state);
 hipError_t launch_bdf_wave(const DevMech& m, const DevEnv& env, double* state, int n_cells,
                            const SolveParams& sp, int* status, camp_cell_stats* stats, int* queue,
-                           int grid, int waves, int stage, hipStream_t stream);
+                           double* kc_glob, int grid, int waves, int stage, hipStream_t stream);
 constexpr size_t kLdsBytes = 160 * 1024;
 hipError_t launch_wave_step(const DevMech& m, int op, int n_cells, const double* kin,
                             const double* yin, double* out, double gamma, hipStream_t stream);

@@ -1,0 +1,49 @@
+"""Writes oracle reference states for sampled cells of the large workloads.
+
+The oracle (CPU FP64 BDF with full Newton and dense LU) needs minutes per cell on the
+largest mechanism, too long to run inside a test, so the GPU parity tests for those
+workloads compare against values this script stores. It calls only `oracle/` and the
+seeded workload generator; nothing here comes from the GPU path.
+
+Usage: python tests/golden/make_oracle_reference.py [c3|c5 ...]
+Writes tests/golden/oracle_<workload>.json: workload, n_cells, sampled cells, tolerances,
+the oracle's final states (user species order) and statuses.
+"""
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+sys.path.insert(0, ROOT)
+
+from oracle.solve import oracle_solve_parallel  # noqa: E402
+from paper_2111_07436_amd import workloads as W  # noqa: E402
+
+RTOL, ATOL = 1e-10, 1e-20
+# (n_cells the workload is generated with, sampled cells): the full-size C3 workload, and a
+# 4096-cell slice of the C5 configuration (its own seeded draws at that size).
+SAMPLES = {
+    "c3": (100_000, [0, 1, 2, 50_000, 99_999]),
+    "c5": (4096, [0, 4095]),
+}
+
+
+def make(name, processes):
+    n, cells = SAMPLES[name]
+    wl = W.make_workload(name, n_cells=n)
+    t = time.time()
+    y, st = oracle_solve_parallel(wl.mech, wl.env, wl.y0, wl.dt, wl.n_calls, RTOL, ATOL, cells, processes)
+    out = {"workload": name, "n_cells": n, "cells": cells, "rtol": RTOL, "atol": ATOL,
+           "n_calls": wl.n_calls, "dt": wl.dt, "status": [int(s) for s in st],
+           "y": [[float(v) for v in row] for row in y], "oracle_seconds": time.time() - t}
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), f"oracle_{name}.json")
+    with open(path, "w") as f:
+        json.dump(out, f)
+    print(f"{path}: {len(cells)} cells, statuses {out['status']}, {out['oracle_seconds']:.0f} s", flush=True)
+
+
+if __name__ == "__main__":
+    names = sys.argv[1:] or list(SAMPLES)
+    for nm in names:
+        make(nm, processes=min(8, os.cpu_count() or 1))

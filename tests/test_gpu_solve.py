@@ -179,3 +179,87 @@ def test_failure_statuses(torch, engine):
     s = st.cpu().numpy()
     assert s[0] == 2 and s[1] == 2, s
     assert np.array_equal(y.cpu().numpy()[0], wl.y0[0])
+
+
+def test_launch_modes_bit_identical(torch):
+    """Table staging, rate-constant placement and cells per workgroup change where data
+    lives, not the arithmetic: every launch mode gives bit-identical states."""
+    from paper_2111_07436_amd import camp
+    for name, n, modes in (("c2", 300, (0, 1, 2, 3)), ("c3", 70, (0, 1, 3))):
+        wl = W.make_workload(name, n_cells=n)
+        m = camp.Mech(wl.mech)
+        ref = None
+        for mode in modes:
+            for waves in (1, 2):
+                log(f"{name} mode {mode} waves {waves}")
+                y = gpu_solve(m, wl, "wave", stage_tables=mode, waves_per_wg=waves, persistent=1,
+                              wg_per_cu=1)
+                if ref is None:
+                    ref = y
+                assert np.array_equal(y, ref), (name, mode, waves)
+
+
+def test_plain_graph_replay_identical(torch):
+    """The plain multi-kernel form replays a captured chunk of step-attempt launches; the
+    states equal those of direct launches."""
+    from paper_2111_07436_amd import camp
+    wl = W.make_workload("c2", n_cells=200)
+    m = camp.Mech(wl.mech)
+    a = gpu_solve(m, wl, "plain", use_graph=0)
+    b = gpu_solve(m, wl, "plain", use_graph=1)
+    c = gpu_solve(m, wl, "plain", use_graph=1)
+    assert np.array_equal(a, b) and np.array_equal(b, c)
+
+
+def test_full_newton_parity(torch):
+    """Full Newton from the start (fresh Jacobian and LU every iteration)."""
+    from paper_2111_07436_amd import camp
+    wl = W.make_workload("c1")
+    m = camp.Mech(wl.mech)
+    y = gpu_solve(m, wl, "wave", full_newton=1)
+    sample = [0, 37, 99]
+    yr, st, _ = oracle_solve(wl.mech, wl.env, wl.y0, wl.dt, wl.n_calls, OR_RTOL, OR_ATOL, cells=sample)
+    assert np.all(st == 0)
+    assert_parity(y[sample], yr, what="c1/full newton")
+
+
+def _golden(name):
+    import json
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", f"oracle_{name}.json")
+    if not os.path.exists(path):
+        pytest.skip(f"{path} not generated (tests/golden/make_oracle_reference.py {name})")
+    with open(path) as f:
+        return json.load(f)
+
+
+def test_c3_full_size_against_stored_oracle(torch):
+    """All 100,000 cells of the multiphase config in the autotuned launch, sampled cells
+    against oracle states written by tests/golden/make_oracle_reference.py."""
+    from paper_2111_07436_amd import camp
+    g = _golden("c3")
+    wl = W.make_workload("c3", n_cells=g["n_cells"])
+    assert wl.n_calls == g["n_calls"] and wl.dt == g["dt"]
+    m = camp.Mech(wl.mech)
+    log(f"c3 full: {wl.n_cells} cells, engine auto")
+    y = gpu_solve(m, wl, "auto")
+    ok = np.asarray(g["status"]) == 0
+    cells = np.asarray(g["cells"])[ok]
+    assert_parity(y[cells], np.asarray(g["y"])[ok], what="c3/full vs stored oracle")
+
+
+def test_c5_sample_against_stored_oracle(torch):
+    """The large mechanism (520 state variables, 5493 fill entries): sampled cells of its
+    4096-cell workload, each engine that runs it, against stored oracle states."""
+    from paper_2111_07436_amd import camp
+    g = _golden("c5")
+    wl = W.make_workload("c5", n_cells=g["n_cells"])
+    ok = np.asarray(g["status"]) == 0
+    cells = np.asarray(g["cells"])[ok]
+    sub = wl.take(cells)
+    m = camp.Mech(sub.mech)
+    for kw in ({"engine": "wave", "stage_tables": 0}, {"engine": "wave", "stage_tables": 3},
+               {"engine": "lane"}):
+        log(f"c5 sample: {len(cells)} cells, {kw}")
+        y = gpu_solve(m, sub, **kw)
+        assert_parity(y, np.asarray(g["y"])[ok], what=f"c5/{kw}")
