@@ -248,21 +248,21 @@ int solve_device_tuned(camp_mech* mh, const DevMech& dm, int n_cells, double* d_
       return CAMP_EINVAL;
     }
     const int waves = std::max(1, tu.waves);
-    const int stage = std::max(0, std::min(3, tu.stage));
+    const int stage = std::max(0, std::min(4, tu.stage));
     if (wave_wg_lds_bytes(dm, waves, stage) > kLdsBytes) {
       set_error("mechanism does not fit the wavefront engine's LDS budget");
       return CAMP_EINVAL;
     }
     const int wg_total = (n_cells + waves - 1) / waves;
-    if (tu.persistent || stage == 3) {
+    if (tu.persistent || stage >= 3) {
       // queue counter, then (mode 3) the rate-constant scratch of every resident wavefront
       const int grid = std::max(1, std::min(wg_total, n_cus() * std::max(1, tu.grid_mult)));
-      const size_t kc_bytes = stage == 3 ? sizeof(double) * (size_t)grid * waves * dm.R : 0;
+      const size_t kc_bytes = stage >= 3 ? sizeof(double) * (size_t)grid * waves * dm.R : 0;
       char* buf = nullptr;
       e = hipMallocAsync((void**)&buf, 256 + kc_bytes, stream);
       if (e != hipSuccess) return hip_fail(e, "hipMallocAsync(queue)");
       int* queue = reinterpret_cast<int*>(buf);
-      double* kc = stage == 3 ? reinterpret_cast<double*>(buf + 256) : nullptr;
+      double* kc = stage >= 3 ? reinterpret_cast<double*>(buf + 256) : nullptr;
       e = launch_fill_int(queue, 1, 0, stream);
       if (e == hipSuccess)
         e = launch_bdf_wave(dm, env, d_state, n_cells, sp, d_status, d_stats, queue, kc, grid,
@@ -278,9 +278,10 @@ int solve_device_tuned(camp_mech* mh, const DevMech& dm, int n_cells, double* d_
   return CAMP_OK;
 }
 
-// Occupancy-driven default: the launch mode and wavefronts per workgroup (<= 8) such that
-// the workgroups resident on one CU hold the most cells, preferring the most tables staged
-// and rate constants in LDS (mode 3 only when it fits more cells).
+// Occupancy-driven default: the launch mode and wavefronts per workgroup such that the
+// workgroups resident on one CU hold the most cells (wavefronts per CU are capped by the
+// registers the mode's kernel uses), preferring the most tables staged and rate constants
+// in LDS at equal counts.
 Tuning default_tuning(const DevMech& dm, int n_cells) {
   Tuning t;
   const bool fits_wave = (dm.N + kWave - 1) / kWave <= 9 && dm.stage &&
@@ -288,9 +289,9 @@ Tuning default_tuning(const DevMech& dm, int n_cells) {
   t.engine = fits_wave ? CAMP_ENGINE_FUSED_WAVE : CAMP_ENGINE_FUSED_LANE;
   t.persistent = 1;
   int best_cells = 0;
-  const int wmax = wave_max_waves(dm.N);   // also the resident wavefronts per CU by VGPRs
   t.stage = -1;
-  for (int stage : {2, 1, 0, 3})
+  for (int stage : {2, 1, 0, 4, 3}) {
+    const int wmax = wave_max_waves(dm.N, stage);   // also the resident wavefronts per CU
     for (int w = 1; w <= wmax; ++w) {
       const size_t b = wave_wg_lds_bytes(dm, w, stage);
       if (b > kLdsBytes) break;
@@ -303,6 +304,7 @@ Tuning default_tuning(const DevMech& dm, int n_cells) {
         t.grid_mult = std::max(1, std::min(wgs, wmax / w));
       }
     }
+  }
   (void)n_cells;
   return t;
 }
@@ -409,8 +411,8 @@ int camp_solve_device(camp_mech* mh, int n_cells, double* d_state, const camp_en
   if (opts && engine != CAMP_ENGINE_AUTO) {
     if (opts->persistent >= 0) tu.persistent = opts->persistent ? 1 : 0;
     if (opts->wg_per_cu > 0) tu.grid_mult = opts->wg_per_cu;
-    if (opts->waves_per_wg > 0) tu.waves = std::min(opts->waves_per_wg, 8);
-    if (opts->stage_tables >= 0) tu.stage = std::min(opts->stage_tables, 3);
+    if (opts->waves_per_wg > 0) tu.waves = std::min(opts->waves_per_wg, 12);
+    if (opts->stage_tables >= 0) tu.stage = std::min(opts->stage_tables, 4);
   }
   return solve_device_tuned(mh, *dm, n_cells, d_state, d_env, sp, opts, d_status, d_stats,
                             (hipStream_t)stream, tu);

@@ -2,10 +2,10 @@
 //
 // On the first call for a bucket it times short trials of each candidate on a copy of the
 // call's own first cells (the caller's arrays are never written by a trial) and caches
-// the fastest. Candidates: the wavefront engine at the two deepest LDS table-staging levels
-// that fit (and with rate constants in global scratch when that fits more cells), 1..8
-// cells per workgroup, a persistent grid sized to the resident capacity or one workgroup
-// per cell batch; the lane-per-cell fused engine only when no wavefront launch fits. With
+// the fastest. Candidates: the wavefront engine in each launch mode (table staging, rate
+// constants in LDS or in global scratch) at the cells per workgroup that keep the most
+// cells resident, with a persistent grid sized to that capacity or one workgroup per cell
+// batch; the lane-per-cell fused engine only when no wavefront launch fits. With
 // CAMP_TUNE_CACHE set to a file path, choices persist across processes (keyed by a hash of
 // the compiled mechanism, the device name and the bucket).
 #include <hip/hip_runtime.h>
@@ -106,31 +106,33 @@ std::vector<Tuning> candidates(const DevMech& dm) {
   std::vector<Tuning> out;
   const bool wave_ok = (dm.N + kWave - 1) / kWave <= 9 && dm.stage;
   if (wave_ok) {
-    const int wmax = wave_max_waves(dm.N);
-    for (int w : {1, 2, 4, 8}) {
-      if (w > wmax) continue;
-      int tried = 0;   // the two most-staged modes that fit, then mode 3 if it holds more cells
-      int best_wgs = 0;
-      for (int stage : {2, 1, 0, 3}) {
+    // per launch mode, the cells per workgroup that keep the most cells resident per CU
+    // (ties: the larger workgroup); persistent, and for the LDS-rate-constant modes also one
+    // workgroup per cell batch
+    for (int stage : {2, 1, 0, 4, 3}) {
+      const int wmax = wave_max_waves(dm.N, stage);
+      Tuning best;
+      int best_cells = 0;
+      for (int w = 1; w <= wmax; ++w) {
         const size_t b = wave_wg_lds_bytes(dm, w, stage);
-        if (b > kLdsBytes) continue;
+        if (b > kLdsBytes) break;
         const int wgs = (int)(kLdsBytes / b);   // resident workgroups per CU by LDS
-        if (stage == 3 ? std::min(wgs * w, wmax) <= std::min(best_wgs * w, wmax) : tried >= 2)
-          continue;
-        if (stage != 3) ++tried;
-        best_wgs = std::max(best_wgs, wgs);
-        Tuning t;
-        t.engine = CAMP_ENGINE_FUSED_WAVE;
-        t.waves = w;
-        t.stage = stage;
-        t.persistent = 1;
-        t.grid_mult = std::max(1, std::min(wgs, std::max(1, wmax / w)));
-        out.push_back(t);
-        if ((w == 1 || w == 8) && stage != 3) {
-          Tuning np = t;
-          np.persistent = 0;
-          out.push_back(np);
+        const int cells = std::min(wgs * w, wmax);
+        if (cells >= best_cells) {
+          best_cells = cells;
+          best.engine = CAMP_ENGINE_FUSED_WAVE;
+          best.waves = w;
+          best.stage = stage;
+          best.persistent = 1;
+          best.grid_mult = std::max(1, std::min(wgs, std::max(1, wmax / w)));
         }
+      }
+      if (best_cells == 0) continue;
+      out.push_back(best);
+      if (stage <= 2) {
+        Tuning np = best;
+        np.persistent = 0;
+        out.push_back(np);
       }
     }
   }

@@ -676,24 +676,27 @@ __device__ void solve_one_cell(const DevMech& m, const DevEnv& env, double* stat
 //   2  whole table block staged in LDS
 //   3  tables from global memory and rate constants in a global per-wavefront scratch
 //      (persistent launches only), for mechanisms whose per-cell LDS is the occupancy limit
-constexpr int kModeKcGlobal = 3;
+//   4  core index tables staged in LDS and rate constants in the global scratch
+// In modes 3 and 4 a mechanism of at most 128 state variables runs a kernel built for
+// three wavefronts per SIMD (at most 168 registers), with up to 12 cells per workgroup.
+__host__ __device__ constexpr bool kc_global(int mode) { return mode >= 3; }
 
 // LDS doubles of one cell: M, y, x, partials/rates, and the rate constants unless mode 3.
 __host__ __device__ inline size_t cell_doubles(const DevMech& m, int mode) {
   const int np = m.n_part > m.R ? m.n_part : m.R;
-  return (size_t)m.Z + 2 * (size_t)m.N + np + (mode == kModeKcGlobal ? 0 : m.R);
+  return (size_t)m.Z + 2 * (size_t)m.N + np + (kc_global(mode) ? 0 : m.R);
 }
 
 // Bytes of the table block staged in LDS in launch mode `mode`.
 __host__ __device__ inline int staged_bytes(const DevMech& m, int mode) {
-  return mode == 2 ? m.stage_bytes : mode == 1 ? m.stage_core_bytes : 0;
+  return mode == 2 ? m.stage_bytes : (mode == 1 || mode == 4) ? m.stage_core_bytes : 0;
 }
 
 // Copies the staged part of the table block into LDS (16-byte units).
 template <int kStage>
 __device__ __forceinline__ Tabs stage_tables(const DevMech& m, double* lds) {
   const char* g = reinterpret_cast<const char*>(m.stage);
-  if (kStage == 0 || kStage == kModeKcGlobal) return Tabs{g, g, m};
+  if (kStage == 0 || kStage == 3) return Tabs{g, g, m};
   const uint4* src = reinterpret_cast<const uint4*>(m.stage);
   uint4* dst = reinterpret_cast<uint4*>(lds);
   const int n16 = staged_bytes(m, kStage) / 16;
@@ -707,15 +710,25 @@ __device__ __forceinline__ Tabs stage_tables(const DevMech& m, double* lds) {
 
 // Up to 3 species per lane the kernel fits 256 VGPRs (two wavefronts per SIMD, workgroups
 // of up to 8 wavefronts); larger states get 512 VGPRs (workgroups of up to 4 wavefronts).
-template <int NPL>
-constexpr int max_waves_per_wg() { return NPL <= 3 ? 8 : 4; }
-int wave_max_waves(int n_state) { return (n_state + kWave - 1) / kWave <= 3 ? 8 : 4; }
+// In modes 3 and 4, up to 2 species per lane the kernel is built for 168 registers (three
+// wavefronts per SIMD, workgroups of up to 12 wavefronts).
+template <int NPL, int kMode>
+constexpr bool occ3() { return NPL <= 2 && kc_global(kMode); }
+template <int NPL, int kMode>
+constexpr int max_waves_per_wg() { return occ3<NPL, kMode>() ? 12 : NPL <= 3 ? 8 : 4; }
+template <int NPL, int kMode>
+constexpr int min_waves_per_simd() { return occ3<NPL, kMode>() ? 3 : 1; }
+int wave_max_waves(int n_state, int mode) {
+  const int npl = (n_state + kWave - 1) / kWave;
+  return (npl <= 2 && kc_global(mode)) ? 12 : npl <= 3 ? 8 : 4;
+}
 
 // blockDim.x = 64 * W: W wavefronts, one cell each. queue != nullptr: persistent grid
 // pulling cells from the counter; else cell = blockIdx.x * W + wavefront. Mode 3 keeps the
 // rate constants at kc_glob + (blockIdx.x * W + wavefront) * R and needs the queue.
 template <int NPL, int kStage>
-__global__ __launch_bounds__(kWave * max_waves_per_wg<NPL>()) void bdf_wave_kernel(
+__global__ __launch_bounds__((kWave * max_waves_per_wg<NPL, kStage>()),
+                             (min_waves_per_simd<NPL, kStage>())) void bdf_wave_kernel(
     DevMech m, DevEnv env, double* state, int n_cells, SolveParams sp, int* status,
     camp_cell_stats* stats, int* queue, double* kc_glob) {
   extern __shared__ double lds[];
@@ -723,7 +736,7 @@ __global__ __launch_bounds__(kWave * max_waves_per_wg<NPL>()) void bdf_wave_kern
   const int W = blockDim.x / kWave, wid = threadIdx.x / kWave, lane = threadIdx.x % kWave;
   double* base = lds + staged_bytes(m, kStage) / 8 + wid * cell_doubles(m, kStage);
   const int np = m.n_part > m.R ? m.n_part : m.R;
-  double* kc = kStage == kModeKcGlobal ? kc_glob + (size_t)(blockIdx.x * W + wid) * m.R
+  double* kc = kc_global(kStage) ? kc_glob + (size_t)(blockIdx.x * W + wid) * m.R
                                        : base + m.Z + 2 * m.N + np;
   const WaveCell<NPL> Wc{m, tab, base, base + m.Z, base + m.Z + m.N, base + m.Z + 2 * m.N, kc, lane};
   if (!queue) {
@@ -771,6 +784,7 @@ hipError_t launch_wave_stage(const DevMech& m, const DevEnv& env, double* state,
     case 1: return launch_wave_npl<NPL, 1>(m, env, state, n_cells, sp, status, stats, queue, kc_glob, grid, waves, lds, stream);
     case 2: return launch_wave_npl<NPL, 2>(m, env, state, n_cells, sp, status, stats, queue, kc_glob, grid, waves, lds, stream);
     case 3: return launch_wave_npl<NPL, 3>(m, env, state, n_cells, sp, status, stats, queue, kc_glob, grid, waves, lds, stream);
+    case 4: return launch_wave_npl<NPL, 4>(m, env, state, n_cells, sp, status, stats, queue, kc_glob, grid, waves, lds, stream);
     default: return hipErrorInvalidValue;
   }
 }
@@ -780,9 +794,9 @@ hipError_t launch_bdf_wave(const DevMech& m, const DevEnv& env, double* state, i
                            double* kc_glob, int grid, int waves, int stage, hipStream_t stream) {
   const size_t lds = wave_wg_lds_bytes(m, waves, stage);
   const int npl = (m.N + kWave - 1) / kWave;
-  if (waves < 1 || waves > wave_max_waves(m.N)) return hipErrorInvalidValue;
-  if (stage < 0 || stage > 3 || !m.stage) return hipErrorInvalidValue;
-  if (stage == kModeKcGlobal && (!queue || !kc_glob)) return hipErrorInvalidValue;
+  if (stage < 0 || stage > 4 || !m.stage) return hipErrorInvalidValue;
+  if (waves < 1 || waves > wave_max_waves(m.N, stage)) return hipErrorInvalidValue;
+  if (kc_global(stage) && (!queue || !kc_glob)) return hipErrorInvalidValue;
   switch (npl) {
     case 1: return launch_wave_stage<1>(m, env, state, n_cells, sp, status, stats, queue, kc_glob, grid, waves, stage, lds, stream);
     case 2: return launch_wave_stage<2>(m, env, state, n_cells, sp, status, stats, queue, kc_glob, grid, waves, stage, lds, stream);

@@ -23,7 +23,7 @@ struct Tuning {
   int grid_mult = 8;         // wave engine: workgroups per CU when persistent
   int waves = 1;             // wave engine: wavefronts (cells) per workgroup
   int stage = 1;             // wave engine launch mode: tables staged in LDS (0 none, 1 index,
-                             // 2 all) or 3 (none; rate constants in global scratch)
+                             // 2 all); 3 / 4 as 0 / 1 with rate constants in global scratch
   double ms = 0.0;           // measured trial time
 };
 
@@ -41,7 +41,7 @@ int hip_fail(hipError_t e, const char* what);
 size_t wave_lds_bytes(const DevMech& m);
 size_t wave_cell_bytes(const DevMech& m);
 size_t wave_wg_lds_bytes(const DevMech& m, int waves, int stage);
-int wave_max_waves(int n_state);
+int wave_max_waves(int n_state, int mode);
 hipError_t launch_bdf_wave(const DevMech& m, const DevEnv& env, double* state, int n_cells,
                            const SolveParams& sp, int* status, camp_cell_stats* stats, int* queue,
                            double* kc_glob, int grid, int waves, int stage, hipStream_t stream);
