@@ -45,7 +45,7 @@ WORKLOADS = {
 }
 
 
-CPU_SAMPLE = {"c1": 100, "c2": 1000, "c3": 256, "c5": 16}
+CPU_SAMPLE = {"c1": 100, "c2": 10000, "c3": 1024, "c5": 128}
 # The plain per-cell form is timed on at most this many cells of the workload (its rate in
 # cell-steps/s does not depend on the count once the GPU is full).
 PLAIN_CELLS = 20_000
@@ -53,6 +53,14 @@ PLAIN_CELLS = 20_000
 
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def _progress(what):
+    """Logs oracle progress about every tenth of the sample."""
+    def cb(done, total):
+        if done == total or done % max(1, total // 10) == 0:
+            log(f"{what}: {done}/{total} cells")
+    return cb
 
 
 def kernel_source_hash():
@@ -160,7 +168,8 @@ def run_gpu(name, engine, steps, warmup, rtol, atol, n_cells=None):
 
 def accuracy(wl, y_gpu, cells, processes):
     from oracle.solve import oracle_solve_parallel
-    yr, st = oracle_solve_parallel(wl.mech, wl.env, wl.y0, wl.dt, wl.n_calls, 1e-10, 1e-20, cells, processes)
+    yr, st = oracle_solve_parallel(wl.mech, wl.env, wl.y0, wl.dt, wl.n_calls, 1e-10, 1e-20, cells, processes,
+                                   progress=_progress("accuracy oracle"))
     ref = yr[st == 0]
     got = y_gpu[np.asarray(cells)[st == 0]]
     big = np.abs(ref) >= 1e-12
@@ -174,11 +183,13 @@ def cpu_baseline(wl, rtol, atol, sample, processes):
     from oracle.solve import oracle_solve_parallel
     cells = np.linspace(0, wl.n_cells - 1, sample).astype(int)
     t = time.perf_counter()
-    _, st = oracle_solve_parallel(wl.mech, wl.env, wl.y0, wl.dt, wl.n_calls, rtol, atol, cells, processes)
+    _, st = oracle_solve_parallel(wl.mech, wl.env, wl.y0, wl.dt, wl.n_calls, rtol, atol, cells, processes,
+                                  progress=_progress("cpu baseline"))
     dt = time.perf_counter() - t
     return {"value": len(cells) * 1 / dt, "unit": "cell-steps/s", "cores": processes, "kind": "oracle",
             "sample": f"{len(cells)} cells evenly strided over the {wl.n_cells}-cell workload, "
-                      f"one host step each, rtol {rtol:g}, atol {atol:g}, one process per core",
+                      f"one host step each, rtol {rtol:g}, atol {atol:g}, one single-threaded "
+                      f"process per core",
             "seconds": dt, "failed": int(np.sum(st != 0))}
 
 
@@ -279,8 +290,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-accuracy", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=0,
-                    help="cells in the CPU-oracle sample (default: about 10-30 s of host CPU work "
-                         "for the workload: c1 100, c2 1000, c3 256, c5 16)")
+                    help="cells in the CPU-oracle sample (default: about 10-30 s on the host's "
+                         "cores for the workload: c1 100, c2 10000, c3 1024, c5 128)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a 1 GiB device copy (for scaling rocprofv3 byte counters)")
     args = ap.parse_args()

@@ -192,6 +192,9 @@ typedef struct {
   int stage_tables;     /* FUSED_WAVE tables in LDS: 0 = none (global), 1 = sparse-index */
                         /* tables, 2 = all (also forcing terms and Jacobian map),      */
                         /* -1 = auto                                                   */
+  int lanes_per_cell;   /* FUSED_WAVE: 64 = one wavefront per cell, 128 or 256 = one     */
+                        /* workgroup of 2 or 4 wavefronts per cell (more than 64 / 128  */
+                        /* state variables), 0 = auto                                   */
   int full_newton;      /* 0 (default): Newton with Jacobian reuse; a cell that fails   */
                         /* (status 1-4) is integrated again from its input with full    */
                         /* Newton. 1: full Newton (fresh Jacobian and LU every iteration)*/

@@ -6,7 +6,6 @@ For each cell independently: compute the rate constants from that cell's environ
 integrates, the final state is returned). ``n_calls`` consecutive host steps restart
 the integrator each call, as each host call is a fresh solve.
 """
-import os
 from concurrent.futures import ProcessPoolExecutor
 
 import numpy as np
@@ -60,9 +59,10 @@ _WORKER = {}
 
 
 def _init_worker(mech, env, y0, dt, n_calls, rtol, atol):
-    os.environ.setdefault("OMP_NUM_THREADS", "1")
-    _WORKER.update(cs=CellSolver(mech), env=env, y0=y0, dt=dt, n_calls=n_calls,
-                   rtol=rtol, atol=atol)
+    # one process per core: keep each worker's BLAS single-threaded
+    from threadpoolctl import threadpool_limits
+    _WORKER.update(limits=threadpool_limits(limits=1), cs=CellSolver(mech), env=env, y0=y0,
+                   dt=dt, n_calls=n_calls, rtol=rtol, atol=atol)
 
 
 def _work(chunk):
@@ -75,18 +75,24 @@ def _work(chunk):
     return res
 
 
-def oracle_solve_parallel(mech, env, y0, dt, n_calls, rtol, atol, cells, processes):
-    """Same as ``oracle_solve`` with cells split over worker processes (one per core)."""
+def oracle_solve_parallel(mech, env, y0, dt, n_calls, rtol, atol, cells, processes, progress=None):
+    """Same as ``oracle_solve`` with cells split over worker processes (one per core).
+    ``progress(done, total)`` is called as cells complete."""
+    from concurrent.futures import as_completed
     cells = list(cells)
-    chunks = [cells[i::processes] for i in range(processes)]
-    chunks = [c for c in chunks if c]
+    per = max(1, len(cells) // (4 * processes))
+    chunks = [cells[i:i + per] for i in range(0, len(cells), per)]
     out = np.empty((len(cells), y0.shape[1]))
     status = np.zeros(len(cells), dtype=np.int32)
     pos = {c: n for n, c in enumerate(cells)}
-    with ProcessPoolExecutor(max_workers=len(chunks), initializer=_init_worker,
+    done = 0
+    with ProcessPoolExecutor(max_workers=min(processes, len(chunks)), initializer=_init_worker,
                              initargs=(mech, env, y0, dt, n_calls, rtol, atol)) as ex:
-        for res in ex.map(_work, chunks):
-            for c, y, s in res:
+        for fut in as_completed([ex.submit(_work, ch) for ch in chunks]):
+            for c, y, s in fut.result():
                 out[pos[c]] = y
                 status[pos[c]] = s
+                done += 1
+            if progress:
+                progress(done, len(cells))
     return out, status

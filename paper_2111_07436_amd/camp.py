@@ -73,7 +73,8 @@ class Opts(C.Structure):
     _fields_ = [("max_order", C.c_int), ("max_steps", C.c_int), ("newton_max_iter", C.c_int),
                 ("h_min", C.c_double), ("h_init", C.c_double), ("engine", C.c_int),
                 ("wg_per_cu", C.c_int), ("persistent", C.c_int), ("use_graph", C.c_int),
-                ("waves_per_wg", C.c_int), ("stage_tables", C.c_int), ("full_newton", C.c_int)]
+                ("waves_per_wg", C.c_int), ("stage_tables", C.c_int), ("lanes_per_cell", C.c_int),
+                ("full_newton", C.c_int)]
 
 
 class CellStats(C.Structure):
@@ -135,10 +136,10 @@ def _stream():
 
 def make_opts(engine="auto", max_order=0, max_steps=0, newton_max_iter=0, h_min=0.0, h_init=0.0,
               wg_per_cu=0, persistent=-1, use_graph=0, waves_per_wg=0, stage_tables=-1,
-              full_newton=0):
+              lanes_per_cell=0, full_newton=0):
     e = ENGINES[engine] if isinstance(engine, str) else int(engine)
     return Opts(max_order, max_steps, newton_max_iter, h_min, h_init, e, wg_per_cu,
-                persistent, use_graph, waves_per_wg, stage_tables, full_newton)
+                persistent, use_graph, waves_per_wg, stage_tables, lanes_per_cell, full_newton)
 
 
 class Mech:

@@ -75,7 +75,9 @@ int upload(camp_mech* mh, int device, DeviceTables& out) {
          o_bwt = add(C.bwd_tasks.data(), sizeof(Task) * C.bwd_tasks.size()),
          o_lup = add(lup.data(), 4 * lup.size()), o_fwp = add(fwp.data(), 4 * fwp.size()),
          o_bwp = add(bwp.data(), 4 * bwp.size()),
-         o_stage = add(mh->stage.bytes.data(), mh->stage.bytes.size());
+         o_stage[3] = {add(mh->stage[0].bytes.data(), mh->stage[0].bytes.size()),
+                       add(mh->stage[1].bytes.data(), mh->stage[1].bytes.size()),
+                       add(mh->stage[2].bytes.data(), mh->stage[2].bytes.size())};
 
   std::vector<char> host(total, 0);
   for (auto& it : items)
@@ -125,30 +127,39 @@ int upload(camp_mech* mh, int device, DeviceTables& out) {
   d.lu_pair = (const int2*)(b + o_lup);
   d.fwd_pair = (const int2*)(b + o_fwp);
   d.bwd_pair = (const int2*)(b + o_bwp);
-  const StageBlock& sb = mh->stage;
-  d.stage = sb.ok ? (const uint8_t*)(b + o_stage) : nullptr;
-  d.stage_bytes = sb.ok ? (int)sb.bytes.size() : 0;
-  d.so_rx = sb.off_rx;
-  d.so_diag = sb.off_diag;
-  d.so_sf = sb.off_sf;
-  d.so_sf_lp = sb.off_sf_lp;
-  d.so_sb = sb.off_sb;
-  d.so_sb_lp = sb.off_sb_lp;
-  d.so_lt = sb.off_lt;
-  d.so_lt_lp = sb.off_lt_lp;
-  d.so_lf = sb.off_lf;
-  d.so_lf_lp = sb.off_lf_lp;
-  d.so_us = sb.off_us;
-  d.n_sf_lev = sb.n_sf_lev;
-  d.n_sb_lev = sb.n_sb_lev;
-  d.n_us = sb.n_us;
-  d.stage_core_bytes = sb.ok ? sb.core_bytes : 0;
-  d.so_ft = sb.off_ft;
-  d.so_ft_coef = sb.off_ft_coef;
-  d.so_jt = sb.off_jt;
-  d.so_jt_coef = sb.off_jt_coef;
-  d.n_ft = sb.n_ft;
-  d.n_jt = sb.n_jt;
+  for (int v = 0; v < 3; ++v) {
+    const StageBlock& sb = mh->stage[v];
+    StageView& w = d.sv[v];
+    w = StageView{};
+    if (!sb.ok) continue;
+    w.base = (const uint8_t*)(b + o_stage[v]);
+    w.bytes = (int)sb.bytes.size();
+    w.core_bytes = sb.core_bytes;
+    w.so_rx = sb.off_rx;
+    w.so_diag = sb.off_diag;
+    w.so_sf = sb.off_sf;
+    w.so_sf_lp = sb.off_sf_lp;
+    w.so_sb = sb.off_sb;
+    w.so_sb_lp = sb.off_sb_lp;
+    w.so_lt = sb.off_lt;
+    w.so_lt_lp = sb.off_lt_lp;
+    w.so_lf = sb.off_lf;
+    w.so_lf_lp = sb.off_lf_lp;
+    w.so_us = sb.off_us;
+    w.n_sf_lev = sb.n_sf_lev;
+    w.n_sb_lev = sb.n_sb_lev;
+    w.n_us = sb.n_us;
+    w.so_ft = sb.off_ft;
+    w.so_ft_coef = sb.off_ft_coef;
+    w.so_jt = sb.off_jt;
+    w.so_jt_coef = sb.off_jt_coef;
+    w.n_ft = sb.n_ft;
+    w.n_jt = sb.n_jt;
+    w.so_ft_lp = sb.off_ft_lp;
+    w.so_jt_lp = sb.off_jt_lp;
+    w.wave_lists = sb.wave_lists;
+  }
+  d.stage = d.sv[0].base;
   out.device = device;
   out.blob = blob;
   out.bytes = total;
@@ -243,13 +254,17 @@ int solve_device_tuned(camp_mech* mh, const DevMech& dm, int n_cells, double* d_
     const int slots = std::max(256, n_cus() * 4 * 64 * 2);
     e = run_fused_lane(dm, env, d_state, n_cells, sp, d_status, d_stats, slots, stream);
   } else {
-    if ((dm.N + kWave - 1) / kWave > 9 || !dm.stage) {
+    if (!wave_lanes_ok(dm.N, 64) || !dm.stage) {
       set_error("wavefront engine supports at most 576 state variables per cell");
       return CAMP_EINVAL;
     }
-    const int waves = std::max(1, tu.waves);
+    if (!wave_lanes_ok(dm.N, tu.lanes)) {
+      set_error("lanes per cell must be 64, 128 (65..640 state variables) or 256 (129..768)");
+      return CAMP_EINVAL;
+    }
+    const int waves = tu.lanes == 64 ? std::max(1, tu.waves) : 1;
     const int stage = std::max(0, std::min(4, tu.stage));
-    if (wave_wg_lds_bytes(dm, waves, stage) > kLdsBytes) {
+    if (wave_wg_lds_bytes(dm, waves, stage, tu.lanes) > kLdsBytes) {
       set_error("mechanism does not fit the wavefront engine's LDS budget");
       return CAMP_EINVAL;
     }
@@ -266,42 +281,48 @@ int solve_device_tuned(camp_mech* mh, const DevMech& dm, int n_cells, double* d_
       e = launch_fill_int(queue, 1, 0, stream);
       if (e == hipSuccess)
         e = launch_bdf_wave(dm, env, d_state, n_cells, sp, d_status, d_stats, queue, kc, grid,
-                            waves, stage, stream);
+                            waves, stage, tu.lanes, stream);
       hipError_t e2 = hipFreeAsync(buf, stream);
       if (e == hipSuccess) e = e2;
     } else {
       e = launch_bdf_wave(dm, env, d_state, n_cells, sp, d_status, d_stats, nullptr, nullptr,
-                          wg_total, waves, stage, stream);
+                          wg_total, waves, stage, tu.lanes, stream);
     }
   }
   if (e != hipSuccess) return hip_fail(e, "solve launch");
   return CAMP_OK;
 }
 
-// Occupancy-driven default: the launch mode and wavefronts per workgroup such that the
-// workgroups resident on one CU hold the most cells (wavefronts per CU are capped by the
-// registers the mode's kernel uses), preferring the most tables staged and rate constants
-// in LDS at equal counts.
+// Occupancy-driven default: lanes per cell, launch mode and cells per workgroup such that
+// the CU runs the most wavefronts (cells resident by LDS, times wavefronts per cell, capped
+// by the registers the kernel uses), preferring fewer lanes per cell, then the most tables
+// staged and rate constants in LDS.
 Tuning default_tuning(const DevMech& dm, int n_cells) {
   Tuning t;
-  const bool fits_wave = (dm.N + kWave - 1) / kWave <= 9 && dm.stage &&
-                         wave_wg_lds_bytes(dm, 1, 0) <= kLdsBytes;
+  const bool fits_wave = wave_lanes_ok(dm.N, 64) && dm.stage &&
+                         wave_wg_lds_bytes(dm, 1, 0, 64) <= kLdsBytes;
   t.engine = fits_wave ? CAMP_ENGINE_FUSED_WAVE : CAMP_ENGINE_FUSED_LANE;
   t.persistent = 1;
-  int best_cells = 0;
+  int best = 0;
   t.stage = -1;
-  for (int stage : {2, 1, 0, 4, 3}) {
-    const int wmax = wave_max_waves(dm.N, stage);   // also the resident wavefronts per CU
-    for (int w = 1; w <= wmax; ++w) {
-      const size_t b = wave_wg_lds_bytes(dm, w, stage);
-      if (b > kLdsBytes) break;
-      const int wgs = (int)(kLdsBytes / b);
-      const int cells = std::min(wgs * w, wmax);
-      if (cells > best_cells) {
-        best_cells = cells;
-        t.waves = w;
-        t.stage = stage;
-        t.grid_mult = std::max(1, std::min(wgs, wmax / w));
+  for (int lanes : {64, 128, 256}) {
+    if (!wave_lanes_ok(dm.N, lanes) || !dm.sv[lanes / 128].base) continue;
+    for (int stage : {2, 1, 0, 4, 3}) {
+      const int wmax = wave_max_waves(dm.N, stage, lanes);
+      const int cap = wave_resident_cells_per_cu(dm.N, stage, lanes);
+      for (int w = 1; w <= wmax; ++w) {
+        const size_t b = wave_wg_lds_bytes(dm, w, stage, lanes);
+        if (b > kLdsBytes) break;
+        const int wgs = (int)(kLdsBytes / b);
+        const int cells = std::min(wgs * w, cap);
+        const int score = cells * (lanes / 64);
+        if (score > best) {
+          best = score;
+          t.lanes = lanes;
+          t.waves = w;
+          t.stage = stage;
+          t.grid_mult = std::max(1, std::min(wgs, cap / w));
+        }
       }
     }
   }
@@ -334,7 +355,7 @@ int camp_mech_load(const camp_reaction* rxns, int n_rxn, const camp_species* spe
       set_error(err);
       return CAMP_EINVAL;
     }
-    mh->stage = build_stage_block(mh->C);
+    for (int v = 0; v < 3; ++v) mh->stage[v] = build_stage_block(mh->C, 1 << v);
   } catch (const std::bad_alloc&) {
     delete mh;
     set_error("out of host memory");
@@ -412,6 +433,7 @@ int camp_solve_device(camp_mech* mh, int n_cells, double* d_state, const camp_en
     if (opts->persistent >= 0) tu.persistent = opts->persistent ? 1 : 0;
     if (opts->wg_per_cu > 0) tu.grid_mult = opts->wg_per_cu;
     if (opts->waves_per_wg > 0) tu.waves = std::min(opts->waves_per_wg, 12);
+    if (opts->lanes_per_cell > 0) tu.lanes = opts->lanes_per_cell;
     if (opts->stage_tables >= 0) tu.stage = std::min(opts->stage_tables, 4);
   }
   return solve_device_tuned(mh, *dm, n_cells, d_state, d_env, sp, opts, d_status, d_stats,

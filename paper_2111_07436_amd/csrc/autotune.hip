@@ -2,9 +2,9 @@
 //
 // On the first call for a bucket it times short trials of each candidate on a copy of the
 // call's own first cells (the caller's arrays are never written by a trial) and caches
-// the fastest. Candidates: the wavefront engine in each launch mode (table staging, rate
-// constants in LDS or in global scratch) at the cells per workgroup that keep the most
-// cells resident, with a persistent grid sized to that capacity or one workgroup per cell
+// the fastest. Candidates: the wavefront engine with one wavefront or one workgroup per
+// cell, in each launch mode (table staging, rate constants in LDS or in global scratch), at
+// the cells per workgroup that keep the most cells resident, with a persistent grid sized to that capacity or one workgroup per cell
 // batch; the lane-per-cell fused engine only when no wavefront launch fits. With
 // CAMP_TUNE_CACHE set to a file path, choices persist across processes (keyed by a hash of
 // the compiled mechanism, the device name and the bucket).
@@ -44,7 +44,7 @@ uint64_t mech_hash(const camp_mech* mh) {
   uint64_t h = 1469598103934665603ull;
   h = fnv(h, &C.n_state, sizeof(int));
   h = fnv(h, &C.n_rxn, sizeof(int));
-  h = fnv(h, mh->stage.bytes.data(), mh->stage.bytes.size());
+  for (const auto& sb : mh->stage) h = fnv(h, sb.bytes.data(), sb.bytes.size());
   for (const RateSpec& r : C.rate) h = fnv(h, &r, sizeof(RateSpec));
   h = fnv(h, C.term_coef.data(), 8 * C.term_coef.size());
   return h;
@@ -79,7 +79,7 @@ bool load_cached(const std::string& key, Tuning* t) {
       continue;
     std::istringstream v(line.substr(key.size() + 1));
     Tuning x;
-    if (v >> x.engine >> x.persistent >> x.grid_mult >> x.waves >> x.stage >> x.ms) {
+    if (v >> x.engine >> x.persistent >> x.grid_mult >> x.waves >> x.stage >> x.lanes >> x.ms) {
       *t = x;
       found = true;   // last entry wins
     }
@@ -92,7 +92,7 @@ void store_cached(const std::string& key, const Tuning& t) {
   if (!path || !*path) return;
   std::ofstream f(path, std::ios::app);
   f << key << '|' << t.engine << ' ' << t.persistent << ' ' << t.grid_mult << ' ' << t.waves << ' '
-    << t.stage << ' ' << t.ms << '\n';
+    << t.stage << ' ' << t.lanes << ' ' << t.ms << '\n';
 }
 
 int n_cus_dev() {
@@ -104,35 +104,40 @@ int n_cus_dev() {
 
 std::vector<Tuning> candidates(const DevMech& dm) {
   std::vector<Tuning> out;
-  const bool wave_ok = (dm.N + kWave - 1) / kWave <= 9 && dm.stage;
+  const bool wave_ok = wave_lanes_ok(dm.N, 64) && dm.stage;
   if (wave_ok) {
-    // per launch mode, the cells per workgroup that keep the most cells resident per CU
-    // (ties: the larger workgroup); persistent, and for the LDS-rate-constant modes also one
-    // workgroup per cell batch
-    for (int stage : {2, 1, 0, 4, 3}) {
-      const int wmax = wave_max_waves(dm.N, stage);
-      Tuning best;
-      int best_cells = 0;
-      for (int w = 1; w <= wmax; ++w) {
-        const size_t b = wave_wg_lds_bytes(dm, w, stage);
-        if (b > kLdsBytes) break;
-        const int wgs = (int)(kLdsBytes / b);   // resident workgroups per CU by LDS
-        const int cells = std::min(wgs * w, wmax);
-        if (cells >= best_cells) {
-          best_cells = cells;
-          best.engine = CAMP_ENGINE_FUSED_WAVE;
-          best.waves = w;
-          best.stage = stage;
-          best.persistent = 1;
-          best.grid_mult = std::max(1, std::min(wgs, std::max(1, wmax / w)));
+    // per lanes-per-cell and launch mode, the cells per workgroup that keep the most cells
+    // resident per CU (ties: the larger workgroup); persistent, and for one wavefront per
+    // cell with rate constants in LDS also one workgroup per cell batch
+    for (int lanes : {64, 128, 256}) {
+      if (!wave_lanes_ok(dm.N, lanes) || !dm.sv[lanes / 128].base) continue;
+      for (int stage : {2, 1, 0, 4, 3}) {
+        const int wmax = wave_max_waves(dm.N, stage, lanes);
+        const int cap = wave_resident_cells_per_cu(dm.N, stage, lanes);
+        Tuning best;
+        int best_cells = 0;
+        for (int w = 1; w <= wmax; ++w) {
+          const size_t b = wave_wg_lds_bytes(dm, w, stage, lanes);
+          if (b > kLdsBytes) break;
+          const int wgs = (int)(kLdsBytes / b);   // resident workgroups per CU by LDS
+          const int cells = std::min(wgs * w, cap);
+          if (cells >= best_cells) {
+            best_cells = cells;
+            best.engine = CAMP_ENGINE_FUSED_WAVE;
+            best.lanes = lanes;
+            best.waves = w;
+            best.stage = stage;
+            best.persistent = 1;
+            best.grid_mult = std::max(1, std::min(wgs, std::max(1, cap / w)));
+          }
         }
-      }
-      if (best_cells == 0) continue;
-      out.push_back(best);
-      if (stage <= 2) {
-        Tuning np = best;
-        np.persistent = 0;
-        out.push_back(np);
+        if (best_cells == 0) continue;
+        out.push_back(best);
+        if (lanes == 64 && stage <= 2) {
+          Tuning np = best;
+          np.persistent = 0;
+          out.push_back(np);
+        }
       }
     }
   }

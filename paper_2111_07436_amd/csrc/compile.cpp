@@ -620,10 +620,48 @@ static std::vector<std::pair<int, T>> interleave_by_dst(const std::vector<std::p
   return out;
 }
 
-StageBlock build_stage_block(const Compiled& C) {
+// Splits one level's (dst, payload) terms into `lists` per-wavefront lists: all terms of a
+// destination go to one list (largest destinations first, to the least-loaded list), each
+// list interleaved by destination. With one list per wavefront of the cell's group, a
+// destination's terms accumulate in one wavefront in a fixed order.
+template <class T>
+static std::vector<std::vector<std::pair<int, T>>> split_by_wave(
+    const std::vector<std::pair<int, T>>& in, int lists) {
+  std::vector<std::vector<std::pair<int, T>>> out(lists);
+  if (lists == 1) {
+    out[0] = interleave_by_dst(in);
+    return out;
+  }
+  std::vector<int> order;
+  std::vector<std::vector<T>> groups;
+  std::vector<int> where;
+  for (auto& e : in) {
+    if ((int)where.size() <= e.first) where.resize(e.first + 1, -1);
+    if (where[e.first] < 0) {
+      where[e.first] = (int)groups.size();
+      groups.emplace_back();
+      order.push_back(e.first);
+    }
+    groups[where[e.first]].push_back(e.second);
+  }
+  std::vector<int> idx(groups.size());
+  std::iota(idx.begin(), idx.end(), 0);
+  std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) { return groups[a].size() > groups[b].size(); });
+  std::vector<size_t> load(lists, 0);
+  for (int g : idx) {
+    const int a = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+    for (auto& v : groups[g]) out[a].push_back({order[g], v});
+    load[a] += groups[g].size();
+  }
+  for (auto& l : out) l = interleave_by_dst(l);
+  return out;
+}
+
+StageBlock build_stage_block(const Compiled& C, int wave_lists) {
   StageBlock sb;
   const int N = C.n_state, Z = C.nnz, R = C.n_rxn;
-  if (N >= 1023 || Z > 65535) return sb;
+  if (N >= 1023 || Z > 65535 || (wave_lists != 1 && wave_lists != 2 && wave_lists != 4)) return sb;
+  sb.wave_lists = wave_lists;
   std::vector<uint8_t>& b = sb.bytes;
   auto put = [&](const void* src, size_t n) {
     size_t off = (b.size() + 15) / 16 * 16;
@@ -649,18 +687,21 @@ StageBlock build_stage_block(const Compiled& C) {
                          const std::vector<int>& pa, const std::vector<int>& pb, int& off,
                          int& off_lp, int& n_lev) {
     std::vector<uint32_t> t, lp(1, 0);
+    n_lev = 0;
     for (size_t l = 0; l + 1 < lptr.size(); ++l) {
       std::vector<std::pair<int, int>> lv;
       for (int i = lptr[l]; i < lptr[l + 1]; ++i)
         for (int q = tasks[i].pbeg; q < tasks[i].pend; ++q) lv.push_back({tasks[i].dst, q});
       if (lv.empty()) continue;
-      for (auto& e : interleave_by_dst(lv)) {
-        t.push_back((uint32_t)e.first | ((uint32_t)pb[e.second] << 16));
-        t.push_back((uint32_t)pa[e.second]);
+      for (auto& list : split_by_wave(lv, wave_lists)) {
+        for (auto& e : list) {
+          t.push_back((uint32_t)e.first | ((uint32_t)pb[e.second] << 16));
+          t.push_back((uint32_t)pa[e.second]);
+        }
+        lp.push_back((uint32_t)(t.size() / 2));
       }
-      lp.push_back((uint32_t)(t.size() / 2));
+      ++n_lev;
     }
-    n_lev = (int)lp.size() - 1;
     off = put(t.data(), 4 * t.size());
     off_lp = put(lp.data(), 4 * lp.size());
   };
@@ -680,9 +721,12 @@ StageBlock build_stage_block(const Compiled& C) {
       const Task& x = C.lu_tasks[i];
       for (int q = x.pbeg; q < x.pend; ++q) lv.push_back({x.dst, q});
     }
-    for (auto& e : interleave_by_dst(lv)) {
-      lt.push_back((uint32_t)e.first | ((uint32_t)C.lu_pa[e.second] << 16));
-      lt.push_back((uint32_t)C.lu_pb[e.second]);
+    for (auto& list : split_by_wave(lv, wave_lists)) {
+      for (auto& e : list) {
+        lt.push_back((uint32_t)e.first | ((uint32_t)C.lu_pa[e.second] << 16));
+        lt.push_back((uint32_t)C.lu_pb[e.second]);
+      }
+      ltp.push_back((uint32_t)(lt.size() / 2));
     }
     for (int i = C.lu_level_ptr[l]; i < C.lu_level_ptr[l + 1]; ++i) {
       const Task& x = C.lu_tasks[i];
@@ -691,7 +735,6 @@ StageBlock build_stage_block(const Compiled& C) {
       else if (is_diag[x.dst])
         lf.push_back((uint32_t)x.dst | (0xFFFFu << 16));
     }
-    ltp.push_back((uint32_t)(lt.size() / 2));
     lfp.push_back((uint32_t)lf.size());
   }
   sb.off_lt = put(lt.data(), 4 * lt.size());
@@ -709,25 +752,26 @@ StageBlock build_stage_block(const Compiled& C) {
   sb.core_bytes = (int)b.size();
   // extension: forcing terms and Jacobian contributions as flat term lists
   if (C.n_partials >= 65536 || R >= 65536) return StageBlock{};
-  std::vector<std::pair<int, uint32_t>> ft, jt;
-  std::vector<int> ft_src, jt_src;
+  std::vector<std::pair<int, int>> ft, jt;
   for (int t = 0; t < N; ++t)
-    for (int q = C.term_ptr[t]; q < C.term_ptr[t + 1]; ++q)
-      ft.push_back({t, (uint32_t)q});
+    for (int q = C.term_ptr[t]; q < C.term_ptr[t + 1]; ++q) ft.push_back({t, q});
   for (int z = 0; z < Z; ++z)
-    for (int q = C.jc_ptr[z]; q < C.jc_ptr[z + 1]; ++q)
-      jt.push_back({z, (uint32_t)q});
-  ft = interleave_by_dst(ft);
-  jt = interleave_by_dst(jt);
-  std::vector<uint32_t> fi, ji;
+    for (int q = C.jc_ptr[z]; q < C.jc_ptr[z + 1]; ++q) jt.push_back({z, q});
+  std::vector<uint32_t> fi, ji, fp(1, 0), jp(1, 0);
   std::vector<double> fc, jcf;
-  for (auto& e : ft) {
-    fi.push_back((uint32_t)e.first | ((uint32_t)C.term_rxn[e.second] << 16));
-    fc.push_back(C.term_coef[e.second]);
+  for (auto& list : split_by_wave(ft, wave_lists)) {
+    for (auto& e : list) {
+      fi.push_back((uint32_t)e.first | ((uint32_t)C.term_rxn[e.second] << 16));
+      fc.push_back(C.term_coef[e.second]);
+    }
+    fp.push_back((uint32_t)fi.size());
   }
-  for (auto& e : jt) {
-    ji.push_back((uint32_t)e.first | ((uint32_t)C.jc_part[e.second] << 16));
-    jcf.push_back(C.jc_coef[e.second]);
+  for (auto& list : split_by_wave(jt, wave_lists)) {
+    for (auto& e : list) {
+      ji.push_back((uint32_t)e.first | ((uint32_t)C.jc_part[e.second] << 16));
+      jcf.push_back(C.jc_coef[e.second]);
+    }
+    jp.push_back((uint32_t)ji.size());
   }
   sb.n_ft = (int)fi.size();
   sb.n_jt = (int)ji.size();
@@ -735,6 +779,8 @@ StageBlock build_stage_block(const Compiled& C) {
   sb.off_jt_coef = put(jcf.data(), 8 * jcf.size());
   sb.off_ft = put(fi.data(), 4 * fi.size());
   sb.off_jt = put(ji.data(), 4 * ji.size());
+  sb.off_ft_lp = put(fp.data(), 4 * fp.size());
+  sb.off_jt_lp = put(jp.data(), 4 * jp.size());
   b.resize((b.size() + 15) / 16 * 16);
   sb.ok = true;
   return sb;

@@ -16,6 +16,17 @@ struct alignas(16) DTask {
   int dst, diag, pbeg, pend;
 };
 
+// One layout of the compact table block: device address, sizes and byte offsets.
+struct StageView {
+  const uint8_t* base;
+  int bytes;        // whole block
+  int core_bytes;   // core prefix (index tables of the sparse steps)
+  int so_rx, so_diag, so_sf, so_sf_lp, so_sb, so_sb_lp, so_lt, so_lt_lp, so_lf, so_lf_lp, so_us;
+  int n_sf_lev, n_sb_lev, n_us;
+  int so_ft, so_ft_coef, so_jt, so_jt_coef, n_ft, n_jt, so_ft_lp, so_jt_lp;
+  int wave_lists;   // per-wavefront term lists per level (1, 2 or 4)
+};
+
 // Device copies of the compiled tables; passed to kernels by value.
 struct DevMech {
   int N, R, Z, n_inst, n_ext, n_part, n_gas;
@@ -47,13 +58,10 @@ struct DevMech {
   const int2* lu_pair;         // (pa, pb)
   const int2* fwd_pair;
   const int2* bwd_pair;
-  // compact latency-critical tables (one block, byte offsets; see StageBlock)
-  const uint8_t* stage;
-  int stage_bytes;        // whole block
-  int stage_core_bytes;   // core prefix (index tables of the sparse steps)
-  int so_rx, so_diag, so_sf, so_sf_lp, so_sb, so_sb_lp, so_lt, so_lt_lp, so_lf, so_lf_lp, so_us;
-  int n_sf_lev, n_sb_lev, n_us;
-  int so_ft, so_ft_coef, so_jt, so_jt_coef, n_ft, n_jt;
+  // compact tables of the wavefront engine (see StageBlock), one layout per group size:
+  // sv[0] one wavefront per cell, sv[1] two, sv[2] four wavefronts (a workgroup) per cell
+  StageView sv[3];
+  const uint8_t* stage;   // sv[0].base, null when the mechanism exceeds the 16-bit layout
 };
 
 // Per-cell environment (device pointers, row-major [cells] / [cells][n_inst]).

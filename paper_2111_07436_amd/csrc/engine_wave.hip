@@ -40,26 +40,72 @@ __device__ __forceinline__ void lds_add(double* p, double v) {
   __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
 }
 
+// The lanes that integrate one cell: one wavefront (G = 64, several cells per workgroup),
+// or a whole workgroup of G / 64 wavefronts (G = 128 or 256, one cell per workgroup).
+// Control decisions come from group-wide reductions, so every lane of the group takes the
+// same path.
+template <int G>
+struct Group {
+  static_assert(G == 64 || G == 128 || G == 256, "lanes per cell");
+  static constexpr int kWaves = G / kWave;
+  // Orders the LDS (and global scratch) traffic of the group's lanes.
+  __device__ static void sync() {
+    if constexpr (G == kWave) wave_sync();
+    else __syncthreads();
+  }
+  // Sum over the group, the same value in every lane. red: kWaves doubles of LDS.
+  __device__ static double sum(double v, double* red) {
+    v = wave_sum(v);
+    if constexpr (G == kWave) {
+      return v;
+    } else {
+      if (threadIdx.x % kWave == 0) red[threadIdx.x / kWave] = v;
+      __syncthreads();
+      double t = red[0];
+#pragma unroll
+      for (int k = 1; k < kWaves; ++k) t += red[k];
+      __syncthreads();
+      return t;
+    }
+  }
+  // Nonzero in any lane of the group.
+  __device__ static int any(int v, double* red) {
+    const int a = wave_or(v);
+    if constexpr (G == kWave) {
+      return a;
+    } else {
+      if (threadIdx.x % kWave == 0) red[threadIdx.x / kWave] = a ? 1.0 : 0.0;
+      __syncthreads();
+      double t = 0.0;
+#pragma unroll
+      for (int k = 0; k < kWaves; ++k) t += red[k];
+      __syncthreads();
+      return t != 0.0;
+    }
+  }
+};
+
 // One update of a term loop: add `v` to entry `dst`.
 struct TermUpdate {
   int dst;
   double v;
 };
 
-// Runs the terms i = lo + lane, lo + lane + 64, ... < hi of a term list in groups of kU:
-// the loads of a group (gather) are all issued before any of its updates (scatter), so
-// their latencies overlap. Only valid where no term of the list reads what another writes.
-template <int kU, class Gather, class Scatter>
+// Runs the terms i = lo + lane, lo + lane + G, ... < hi of a term list (G lanes) in groups
+// of kU: the loads of a group (gather) are all issued before any of its updates (scatter),
+// so their latencies overlap. Only valid where no term of the list reads what another
+// writes.
+template <int kU, int G, class Gather, class Scatter>
 __device__ __forceinline__ void for_terms(int lo, int hi, int lane, Gather gather, Scatter scatter) {
   int i = lo + lane;
-  for (; i + (kU - 1) * kWave < hi; i += kU * kWave) {
+  for (; i + (kU - 1) * G < hi; i += kU * G) {
     TermUpdate it[kU];
 #pragma unroll
-    for (int u = 0; u < kU; ++u) it[u] = gather(i + u * kWave);
+    for (int u = 0; u < kU; ++u) it[u] = gather(i + u * G);
 #pragma unroll
     for (int u = 0; u < kU; ++u) scatter(it[u]);
   }
-  for (; i < hi; i += kWave) scatter(gather(i));
+  for (; i < hi; i += G) scatter(gather(i));
 }
 
 constexpr int kTermBatch = 4;
@@ -88,30 +134,64 @@ __device__ __forceinline__ int level_ptr(const LevelPtrs& p, int l, Ptr ptr) {
   return uniform(ptr(l));
 }
 
+// Bounds of one wavefront's term list in each level of a table with kW lists per level
+// (list a of level l spans [ptr(kW l + a), ptr(kW l + a + 1))), held in registers like
+// LevelPtrs: lane k holds the bounds of levels k and k + 64.
+struct LevelRange {
+  int s0, e0, s1, e1;
+};
+
+template <int kW, class Ptr>
+__device__ __forceinline__ LevelRange load_ranges(int nlev, int wid, Ptr ptr) {
+  const int l = threadIdx.x % kWave;
+  LevelRange r{0, 0, 0, 0};
+  if (l < nlev) {
+    r.s0 = ptr(kW * l + wid);
+    r.e0 = ptr(kW * l + wid + 1);
+  }
+  if (l + kWave < nlev) {
+    r.s1 = ptr(kW * (l + kWave) + wid);
+    r.e1 = ptr(kW * (l + kWave) + wid + 1);
+  }
+  return r;
+}
+
+template <int kW, class Ptr>
+__device__ __forceinline__ int2 level_range(const LevelRange& r, int l, int wid, Ptr ptr) {
+  if (l < kWave)
+    return make_int2(__builtin_amdgcn_readlane(r.s0, l), __builtin_amdgcn_readlane(r.e0, l));
+  if (l < 2 * kWave)
+    return make_int2(__builtin_amdgcn_readlane(r.s1, l - kWave),
+                     __builtin_amdgcn_readlane(r.e1, l - kWave));
+  return make_int2(uniform(ptr(kW * l + wid)), uniform(ptr(kW * l + wid + 1)));
+}
+
 // Accessors of the compact table block: the core tables through `b`, the forcing-term and
 // Jacobian-contribution extension through `e`; each base is LDS (staged) or global memory.
 struct Tabs {
   const char* b;
   const char* e;
-  const DevMech& m;
-  __device__ uint32_t ft(int i) const { return reinterpret_cast<const uint32_t*>(e + m.so_ft)[i]; }
-  __device__ double ft_coef(int i) const { return reinterpret_cast<const double*>(e + m.so_ft_coef)[i]; }
-  __device__ uint32_t jt(int i) const { return reinterpret_cast<const uint32_t*>(e + m.so_jt)[i]; }
-  __device__ double jt_coef(int i) const { return reinterpret_cast<const double*>(e + m.so_jt_coef)[i]; }
-  __device__ uint32_t rx(int k) const { return reinterpret_cast<const uint32_t*>(b + m.so_rx)[k]; }
-  __device__ int dg(int t) const { return reinterpret_cast<const uint16_t*>(b + m.so_diag)[t]; }
-  __device__ uint2 sf(int i) const { return reinterpret_cast<const uint2*>(b + m.so_sf)[i]; }
-  __device__ int sf_lp(int l) const { return (int)reinterpret_cast<const uint32_t*>(b + m.so_sf_lp)[l]; }
-  __device__ uint2 sb(int i) const { return reinterpret_cast<const uint2*>(b + m.so_sb)[i]; }
-  __device__ int sb_lp(int l) const { return (int)reinterpret_cast<const uint32_t*>(b + m.so_sb_lp)[l]; }
-  __device__ uint2 lt(int i) const { return reinterpret_cast<const uint2*>(b + m.so_lt)[i]; }
-  __device__ int lt_lp(int l) const { return (int)reinterpret_cast<const uint32_t*>(b + m.so_lt_lp)[l]; }
-  __device__ uint32_t lf(int i) const { return reinterpret_cast<const uint32_t*>(b + m.so_lf)[i]; }
-  __device__ int lf_lp(int l) const { return (int)reinterpret_cast<const uint32_t*>(b + m.so_lf_lp)[l]; }
-  __device__ uint32_t us(int i) const { return reinterpret_cast<const uint32_t*>(b + m.so_us)[i]; }
+  const StageView& v;
+  __device__ uint32_t ft(int i) const { return reinterpret_cast<const uint32_t*>(e + v.so_ft)[i]; }
+  __device__ double ft_coef(int i) const { return reinterpret_cast<const double*>(e + v.so_ft_coef)[i]; }
+  __device__ uint32_t jt(int i) const { return reinterpret_cast<const uint32_t*>(e + v.so_jt)[i]; }
+  __device__ int ft_lp(int a) const { return (int)reinterpret_cast<const uint32_t*>(e + v.so_ft_lp)[a]; }
+  __device__ int jt_lp(int a) const { return (int)reinterpret_cast<const uint32_t*>(e + v.so_jt_lp)[a]; }
+  __device__ double jt_coef(int i) const { return reinterpret_cast<const double*>(e + v.so_jt_coef)[i]; }
+  __device__ uint32_t rx(int k) const { return reinterpret_cast<const uint32_t*>(b + v.so_rx)[k]; }
+  __device__ int dg(int t) const { return reinterpret_cast<const uint16_t*>(b + v.so_diag)[t]; }
+  __device__ uint2 sf(int i) const { return reinterpret_cast<const uint2*>(b + v.so_sf)[i]; }
+  __device__ int sf_lp(int l) const { return (int)reinterpret_cast<const uint32_t*>(b + v.so_sf_lp)[l]; }
+  __device__ uint2 sb(int i) const { return reinterpret_cast<const uint2*>(b + v.so_sb)[i]; }
+  __device__ int sb_lp(int l) const { return (int)reinterpret_cast<const uint32_t*>(b + v.so_sb_lp)[l]; }
+  __device__ uint2 lt(int i) const { return reinterpret_cast<const uint2*>(b + v.so_lt)[i]; }
+  __device__ int lt_lp(int l) const { return (int)reinterpret_cast<const uint32_t*>(b + v.so_lt_lp)[l]; }
+  __device__ uint32_t lf(int i) const { return reinterpret_cast<const uint32_t*>(b + v.so_lf)[i]; }
+  __device__ int lf_lp(int l) const { return (int)reinterpret_cast<const uint32_t*>(b + v.so_lf_lp)[l]; }
+  __device__ uint32_t us(int i) const { return reinterpret_cast<const uint32_t*>(b + v.so_us)[i]; }
 };
 
-template <int NPL>
+template <int NPL, int G>
 struct WaveCell {
   // Terms per lane issued together in the LU and sweep levels: levels of large mechanisms
   // hold several terms per lane, small ones rarely more than one.
@@ -123,24 +203,31 @@ struct WaveCell {
   double* xl;
   double* P;
   double* kc;
-  int lane;
+  double* red;   // reduction scratch of the group (8 doubles of LDS)
+  int lane;      // 0 .. G-1
+  static constexpr int kW = G / kWave;   // wavefronts per cell = term lists per level
+  __device__ static int wlane() { return threadIdx.x % kWave; }
+  __device__ static int wid() { return (threadIdx.x % G) / kWave; }
+
+  __device__ void sync() const { Group<G>::sync(); }
+  __device__ int any(int v) const { return Group<G>::any(v, red); }
 
   __device__ double wrms(const double (&v)[NPL], const double (&w)[NPL]) const {
     double s = 0.0;
 #pragma unroll
     for (int i = 0; i < NPL; ++i)
-      if (lane + kWave * i < m.N) {
+      if (lane + G * i < m.N) {
         double a = v[i] * w[i];
         s += a * a;
       }
-    return sqrt(wave_sum(s) / m.N);
+    return sqrt(Group<G>::sum(s, red) / m.N);
   }
 
   // P[k] = r_k from yl; then f for owned species, accumulated term by term (one term per
   // lane) in xl, which no caller holds live across this call. yl must be visible to all
   // lanes.
   __device__ void forcing(double (&f)[NPL]) const {
-    for (int k = lane; k < m.R; k += kWave) {
+    for (int k = lane; k < m.R; k += G) {
       const uint32_t v = tb.rx(k);
       const int a = v & 0x3FF, b = (v >> 10) & 0x3FF, c = (v >> 20) & 0x3FF;
       double r = kc[k];
@@ -149,28 +236,28 @@ struct WaveCell {
       if (c != 0x3FF) r *= yl[c];
       P[k] = r;
     }
-    for (int t = lane; t < m.N; t += kWave) xl[t] = 0.0;
-    wave_sync();
-    for_terms<kTermBatch>(
-        0, m.n_ft, lane,
+    for (int t = lane; t < m.N; t += G) xl[t] = 0.0;
+    sync();
+    for_terms<kTermBatch, kWave>(
+        uniform(tb.ft_lp(wid())), uniform(tb.ft_lp(wid() + 1)), wlane(),
         [&](int i) {
           const uint32_t e = tb.ft(i);
           return TermUpdate{(int)(e & 0xFFFF), tb.ft_coef(i) * P[e >> 16]};
         },
         [&](const TermUpdate& u) { lds_add(&xl[u.dst], u.v); });
-    wave_sync();
+    sync();
 #pragma unroll
     for (int i = 0; i < NPL; ++i) {
-      const int t = lane + kWave * i;
+      const int t = lane + G * i;
       f[i] = t < m.N ? xl[t] : 0.0;
     }
-    wave_sync();
+    sync();
   }
 
   // M = I - c J(yl) in the filled pattern (fill slots 0 off the diagonal), accumulated
   // contribution by contribution (one per lane).
   __device__ void newton_matrix(double c) const {
-    for (int k = lane; k < m.R; k += kWave) {
+    for (int k = lane; k < m.R; k += G) {
       const uint32_t v = tb.rx(k);
       const int a = v & 0x3FF, b = (v >> 10) & 0x3FF, cc = (v >> 20) & 0x3FF;
       const double kk = kc[k];
@@ -181,19 +268,19 @@ struct WaveCell {
       if (b != 0x3FF) P[base + 1] = kk * ya * yc;
       if (cc != 0x3FF) P[base + 2] = kk * ya * yb;
     }
-    for (int s = lane; s < m.Z; s += kWave) M[s] = 0.0;
-    wave_sync();
+    for (int s = lane; s < m.Z; s += G) M[s] = 0.0;
+    sync();
     const double mc = -c;
-    for_terms<kTermBatch>(
-        0, m.n_jt, lane,
+    for_terms<kTermBatch, kWave>(
+        uniform(tb.jt_lp(wid())), uniform(tb.jt_lp(wid() + 1)), wlane(),
         [&](int i) {
           const uint32_t e = tb.jt(i);
           return TermUpdate{(int)(e & 0xFFFF), mc * tb.jt_coef(i) * P[e >> 16]};
         },
         [&](const TermUpdate& u) { lds_add(&M[u.dst], u.v); });
-    wave_sync();
-    for (int t = lane; t < m.N; t += kWave) M[tb.dg(t)] += 1.0;
-    wave_sync();
+    sync();
+    for (int t = lane; t < m.N; t += G) M[tb.dg(t)] += 1.0;
+    sync();
   }
 
   // In-place Crout LU of M, one dependency level at a time: the level's product terms in
@@ -203,47 +290,46 @@ struct WaveCell {
   // pivot is not a finite nonzero.
   __device__ int lu() const {
     const int L = m.lu_levels;
-    const LevelPtrs tp = load_levels(L, [&](int l) { return tb.lt_lp(l); });
+    auto ltp = [&](int k) { return tb.lt_lp(k); };
+    const LevelRange tr = load_ranges<kW>(L, wid(), ltp);
     const LevelPtrs fp = load_levels(L + 1, [&](int l) { return tb.lf_lp(l); });
     int fhi = level_ptr(fp, 1, [&](int l) { return tb.lf_lp(l); });
-    for (int i = lane; i < fhi; i += kWave) {
+    for (int i = lane; i < fhi; i += G) {
       const int d = tb.lf(i) & 0xFFFF;
       M[d] = 1.0 / M[d];
     }
-    wave_sync();
-    int tlo = 0;
+    sync();
     for (int l = 0; l < L; ++l) {
-      const int thi = level_ptr(tp, l + 1, [&](int k) { return tb.lt_lp(k); });
-      for_terms<kLevelBatch>(
-          tlo, thi, lane,
+      const int2 r = level_range<kW>(tr, l, wid(), ltp);
+      for_terms<kLevelBatch, kWave>(
+          r.x, r.y, wlane(),
           [&](int i) {
             const uint2 e = tb.lt(i);
             return TermUpdate{(int)(e.x & 0xFFFF), M[e.x >> 16] * M[e.y]};
           },
           [&](const TermUpdate& u) { lds_add(&M[u.dst], -u.v); });
-      tlo = thi;
-      wave_sync();
+      sync();
       const int flo = fhi;
       fhi = level_ptr(fp, l + 2, [&](int k) { return tb.lf_lp(k); });
       if (flo == fhi) continue;
-      for (int i = flo + lane; i < fhi; i += kWave) {
+      for (int i = flo + lane; i < fhi; i += G) {
         const uint32_t e = tb.lf(i);
         const int dst = e & 0xFFFF, pv = e >> 16;
         M[dst] = pv == 0xFFFF ? 1.0 / M[dst] : M[dst] * M[pv];
       }
-      wave_sync();
+      sync();
     }
-    for (int i = lane; i < m.n_us; i += kWave) {
+    for (int i = lane; i < tb.v.n_us; i += G) {
       const uint32_t e = tb.us(i);
       M[e & 0xFFFF] *= M[e >> 16];
     }
     int bad = 0;
-    for (int t = lane; t < m.N; t += kWave) {
+    for (int t = lane; t < m.N; t += G) {
       const double r = M[tb.dg(t)];
       if (!(fabs(r) > 0.0) || !isfinite(r)) bad = 1;
     }
-    wave_sync();
-    return !wave_or(bad);
+    sync();
+    return !any(bad);
   }
 
   __device__ int newton_matrix_lu(double c) const {
@@ -254,43 +340,41 @@ struct WaveCell {
   // Conversions between the factor form lu() leaves and the conventional one (unit L
   // strictly below the diagonal, U on and above it).
   __device__ void factors_to_conventional() const {
-    for (int i = lane; i < m.n_us; i += kWave) {
+    for (int i = lane; i < tb.v.n_us; i += G) {
       const uint32_t e = tb.us(i);
       M[e & 0xFFFF] /= M[e >> 16];
     }
-    wave_sync();
-    for (int t = lane; t < m.N; t += kWave) M[tb.dg(t)] = 1.0 / M[tb.dg(t)];
-    wave_sync();
+    sync();
+    for (int t = lane; t < m.N; t += G) M[tb.dg(t)] = 1.0 / M[tb.dg(t)];
+    sync();
   }
   __device__ void factors_from_conventional() const {
-    for (int t = lane; t < m.N; t += kWave) M[tb.dg(t)] = 1.0 / M[tb.dg(t)];
-    wave_sync();
-    for (int i = lane; i < m.n_us; i += kWave) {
+    for (int t = lane; t < m.N; t += G) M[tb.dg(t)] = 1.0 / M[tb.dg(t)];
+    sync();
+    for (int i = lane; i < tb.v.n_us; i += G) {
       const uint32_t e = tb.us(i);
       M[e & 0xFFFF] *= M[e >> 16];
     }
-    wave_sync();
+    sync();
   }
 
   // One triangular sweep over the unit-diagonal factor: x[dst] -= M[slot] * x[src] for
   // the terms of each level, one term per lane.
   template <bool kForward>
   __device__ void sweep() const {
-    const int nlev = kForward ? m.n_sf_lev : m.n_sb_lev;
+    const int nlev = kForward ? tb.v.n_sf_lev : tb.v.n_sb_lev;
     auto lp = [&](int l) { return kForward ? tb.sf_lp(l) : tb.sb_lp(l); };
-    const LevelPtrs p = load_levels(nlev, lp);
-    int lo = 0;
+    const LevelRange p = load_ranges<kW>(nlev, wid(), lp);
     for (int l = 0; l < nlev; ++l) {
-      const int hi = level_ptr(p, l + 1, lp);
-      for_terms<kLevelBatch>(
-          lo, hi, lane,
+      const int2 r = level_range<kW>(p, l, wid(), lp);
+      for_terms<kLevelBatch, kWave>(
+          r.x, r.y, wlane(),
           [&](int i) {
             const uint2 e = kForward ? tb.sf(i) : tb.sb(i);
             return TermUpdate{(int)(e.x & 0xFFFF), M[e.y] * xl[e.x >> 16]};
           },
           [&](const TermUpdate& u) { lds_add(&xl[u.dst], -u.v); });
-      lo = hi;
-      wave_sync();
+      sync();
     }
   }
 
@@ -298,8 +382,8 @@ struct WaveCell {
   // backward sweep.
   __device__ void solve() const {
     sweep<true>();
-    for (int t = lane; t < m.N; t += kWave) xl[t] *= M[tb.dg(t)];
-    wave_sync();
+    for (int t = lane; t < m.N; t += G) xl[t] *= M[tb.dg(t)];
+    sync();
     sweep<false>();
   }
 };
@@ -332,9 +416,9 @@ __device__ __forceinline__ void rescale_hist(double (&D)[kHist][NPL], int q, dou
 // LDS; `bad` flags a non-finite rate constant on this lane). full != 0: full Newton, with a
 // fresh Jacobian and LU at every iteration; else Newton with Jacobian reuse. On success
 // the state row is overwritten; on failure it is left as it was.
-template <int NPL>
+template <int NPL, int G>
 __device__ __forceinline__ int integrate(const DevMech& m, double* yrow, const SolveParams& sp, int bad, int full,
-                         camp_cell_stats& cs, const WaveCell<NPL>& W) {
+                         camp_cell_stats& cs, const WaveCell<NPL, G>& W) {
   const int lane = W.lane;
   const int N = m.N;
   int status = ST_OK;
@@ -343,7 +427,7 @@ __device__ __forceinline__ int integrate(const DevMech& m, double* yrow, const S
   double D[kHist][NPL];
 #pragma unroll
   for (int i = 0; i < NPL; ++i) {
-    const int t = lane + kWave * i;
+    const int t = lane + G * i;
     const double v = t < N ? yrow[m.perm[t]] : 0.0;
     if (t < N) {
       W.yl[t] = v;
@@ -353,8 +437,8 @@ __device__ __forceinline__ int integrate(const DevMech& m, double* yrow, const S
 #pragma unroll
     for (int j = 1; j < kHist; ++j) D[j][i] = 0.0;
   }
-  wave_sync();
-  if (wave_or(bad)) status = ST_NONFINITE;
+  W.sync();
+  if (W.any(bad)) status = ST_NONFINITE;
 
   const double span = sp.dt;
   double w[NPL], f0[NPL], d[NPL];
@@ -368,7 +452,7 @@ __device__ __forceinline__ int integrate(const DevMech& m, double* yrow, const S
       const double s = sp.atol + sp.rtol * fabs(D[0][i]);
       w[i] = s > 0.0 ? 1.0 / s : 0.0;
     }
-    if (wave_or(nf)) status = ST_NONFINITE;
+    if (W.any(nf)) status = ST_NONFINITE;
   }
   double h = 0.0;
   if (status == ST_OK) {
@@ -377,10 +461,10 @@ __device__ __forceinline__ int integrate(const DevMech& m, double* yrow, const S
     const double h0 = starting_step_h0(d0, d1, span);
 #pragma unroll
     for (int i = 0; i < NPL; ++i) {
-      const int t = lane + kWave * i;
+      const int t = lane + G * i;
       if (t < N) W.yl[t] = D[0][i] + h0 * f0[i];
     }
-    wave_sync();
+    W.sync();
     double f1[NPL];
     W.forcing(f1);
     cs.n_f++;
@@ -407,9 +491,9 @@ __device__ __forceinline__ int integrate(const DevMech& m, double* yrow, const S
 #pragma unroll
     for (int i = 0; i < NPL; ++i) {
       w[i] = 1.0 / (sp.rtol * fabs(D[0][i]) + sp.atol);
-      if (lane + kWave * i < N && !isfinite(w[i])) nfw = 1;
+      if (lane + G * i < N && !isfinite(w[i])) nfw = 1;
     }
-    if (wave_or(nfw)) {
+    if (W.any(nfw)) {
       status = ST_NONFINITE;
       break;
     }
@@ -435,10 +519,10 @@ __device__ __forceinline__ int integrate(const DevMech& m, double* yrow, const S
         psi[i] = ps / gq;
         yv[i] = s;
         d[i] = 0.0;
-        const int tt = lane + kWave * i;
+        const int tt = lane + G * i;
         if (tt < N) W.yl[tt] = s;
       }
-      wave_sync();
+      W.sync();
       int fresh = 0, lu_ok = 1;
       if (force_lu || !lu_valid || fabs(c / c_lu - 1.0) > kLuGammaDrift || lu_age >= kLuMaxAge) {
         lu_ok = W.newton_matrix_lu(c);
@@ -458,10 +542,10 @@ __device__ __forceinline__ int integrate(const DevMech& m, double* yrow, const S
           if (it > 0) {
 #pragma unroll
             for (int i = 0; i < NPL; ++i) {
-              const int tt = lane + kWave * i;
+              const int tt = lane + G * i;
               if (tt < N) W.yl[tt] = yv[i];
             }
-            wave_sync();
+            W.sync();
           }
           if (full && (it > 0 || !fresh)) {
             lu_ok = W.newton_matrix_lu(c);   // Jacobian at the current iterate
@@ -481,22 +565,22 @@ __device__ __forceinline__ int integrate(const DevMech& m, double* yrow, const S
           int nf = 0;
 #pragma unroll
           for (int i = 0; i < NPL; ++i) {
-            const int tt = lane + kWave * i;
+            const int tt = lane + G * i;
             if (tt < N) {
               if (!isfinite(f[i])) nf = 1;
               W.xl[tt] = c * f[i] - psi[i] - d[i];
             }
           }
-          if (wave_or(nf)) { nonfin = 1; break; }
-          wave_sync();
+          if (W.any(nf)) { nonfin = 1; break; }
+          W.sync();
           W.solve();
           double dl[NPL];
 #pragma unroll
           for (int i = 0; i < NPL; ++i) {
-            const int tt = lane + kWave * i;
+            const int tt = lane + G * i;
             dl[i] = tt < N ? W.xl[tt] * scale : 0.0;
           }
-          wave_sync();
+          W.sync();
           const double dn = W.wrms(dl, w);
           cs.newton_iters++;
 #pragma unroll
@@ -529,8 +613,8 @@ __device__ __forceinline__ int integrate(const DevMech& m, double* yrow, const S
       int neg = 0;
 #pragma unroll
       for (int i = 0; i < NPL; ++i)
-        if (lane + kWave * i < N && yv[i] * w[i] < -1.0) neg = 1;
-      if (wave_or(neg)) {
+        if (lane + G * i < N && yv[i] * w[i] < -1.0) neg = 1;
+      if (W.any(neg)) {
         cs.rejected++;
         rescale_hist(D, q, kConstraintFactor);
         h *= kConstraintFactor;
@@ -549,10 +633,10 @@ __device__ __forceinline__ int integrate(const DevMech& m, double* yrow, const S
           // restart at order 1 from y_n with a much smaller step: D[1] = h f(y_n)
 #pragma unroll
           for (int i = 0; i < NPL; ++i) {
-            const int tt = lane + kWave * i;
+            const int tt = lane + G * i;
             if (tt < N) W.yl[tt] = D[0][i];
           }
-          wave_sync();
+          W.sync();
           double fn[NPL];
           W.forcing(fn);
           cs.n_f++;
@@ -626,7 +710,7 @@ __device__ __forceinline__ int integrate(const DevMech& m, double* yrow, const S
   if (status == ST_OK) {
 #pragma unroll
     for (int i = 0; i < NPL; ++i) {
-      const int tt = lane + kWave * i;
+      const int tt = lane + G * i;
       if (tt < N) yrow[m.perm[tt]] = D[0][i];
     }
   }
@@ -637,10 +721,10 @@ __device__ __forceinline__ int integrate(const DevMech& m, double* yrow, const S
 // Rate constants, then the integration; a cell whose integration fails (too many steps,
 // step below the minimum, repeated error-test or Newton failures) is integrated again from
 // its input: with full Newton, then with full Newton and a tighter absolute tolerance.
-template <int NPL>
+template <int NPL, int G>
 __device__ void solve_one_cell(const DevMech& m, const DevEnv& env, double* state, int cell,
                                const SolveParams& sp, int* status_out, camp_cell_stats* stats_out,
-                               const WaveCell<NPL>& W) {
+                               const WaveCell<NPL, G>& W) {
   const int lane = W.lane;
   camp_cell_stats cs = {0, 0, 0, 0, 0, 0, 0, 0};
   const double Tk = env.T[cell], Pp = env.P[cell];
@@ -649,7 +733,7 @@ __device__ void solve_one_cell(const DevMech& m, const DevEnv& env, double* stat
   const double* mas = env.mass ? env.mass + (size_t)cell * m.n_inst : nullptr;
   const double* ovr = env.override_ ? env.override_ + (size_t)cell * m.n_ext : nullptr;
   int bad = 0;
-  for (int k = lane; k < m.R; k += kWave) {
+  for (int k = lane; k < m.R; k += G) {
     const double v = rate_constant(m, k, Tk, Pp, cz, rad, mas, ovr);
     W.kc[k] = v;
     if (!isfinite(v)) bad = 1;
@@ -660,14 +744,14 @@ __device__ void solve_one_cell(const DevMech& m, const DevEnv& env, double* stat
   for (int attempt = sp.full_newton ? 1 : 0; attempt < kAttempts; ++attempt) {
     SolveParams spa = sp;
     if (attempt == 2) spa.atol *= kRetryAtolFactor;
-    status = integrate<NPL>(m, yrow, spa, bad, attempt > 0, cs, W);
+    status = integrate<NPL, G>(m, yrow, spa, bad, attempt > 0, cs, W);
     if (status < ST_MAX_STEPS || status > ST_NEWTON_FAIL) break;
   }
   if (lane == 0) {
     status_out[cell] = status;
     if (stats_out) stats_out[cell] = cs;
   }
-  wave_sync();
+  W.sync();
 }
 
 // Launch modes of the wavefront engine (table staging and where rate constants live):
@@ -681,75 +765,108 @@ __device__ void solve_one_cell(const DevMech& m, const DevEnv& env, double* stat
 // three wavefronts per SIMD (at most 168 registers), with up to 12 cells per workgroup.
 __host__ __device__ constexpr bool kc_global(int mode) { return mode >= 3; }
 
-// LDS doubles of one cell: M, y, x, partials/rates, and the rate constants unless mode 3.
+// LDS doubles of one cell: M [Z], y [N], x [N], partials/rates, 8 doubles of group
+// scratch, and the rate constants unless they live in global scratch (modes 3, 4).
 __host__ __device__ inline size_t cell_doubles(const DevMech& m, int mode) {
   const int np = m.n_part > m.R ? m.n_part : m.R;
-  return (size_t)m.Z + 2 * (size_t)m.N + np + (kc_global(mode) ? 0 : m.R);
+  return (size_t)m.Z + 2 * (size_t)m.N + np + 8 + (kc_global(mode) ? 0 : m.R);
 }
 
 // Bytes of the table block staged in LDS in launch mode `mode`.
-__host__ __device__ inline int staged_bytes(const DevMech& m, int mode) {
-  return mode == 2 ? m.stage_bytes : (mode == 1 || mode == 4) ? m.stage_core_bytes : 0;
+__host__ __device__ inline int staged_bytes(const StageView& v, int mode) {
+  return mode == 2 ? v.bytes : (mode == 1 || mode == 4) ? v.core_bytes : 0;
 }
 
 // Copies the staged part of the table block into LDS (16-byte units).
 template <int kStage>
-__device__ __forceinline__ Tabs stage_tables(const DevMech& m, double* lds) {
-  const char* g = reinterpret_cast<const char*>(m.stage);
-  if (kStage == 0 || kStage == 3) return Tabs{g, g, m};
-  const uint4* src = reinterpret_cast<const uint4*>(m.stage);
+__device__ __forceinline__ Tabs stage_tables(const StageView& v, double* lds) {
+  const char* g = reinterpret_cast<const char*>(v.base);
+  if (kStage == 0 || kStage == 3) return Tabs{g, g, v};
+  const uint4* src = reinterpret_cast<const uint4*>(v.base);
   uint4* dst = reinterpret_cast<uint4*>(lds);
-  const int n16 = staged_bytes(m, kStage) / 16;
+  const int n16 = staged_bytes(v, kStage) / 16;
   for (int i = threadIdx.x; i < n16; i += blockDim.x) dst[i] = src[i];
   __syncthreads();
   const char* l = reinterpret_cast<const char*>(lds);
-  return Tabs{l, kStage == 2 ? l : g, m};
+  return Tabs{l, kStage == 2 ? l : g, v};
 }
 
 }  // namespace
 
-// Up to 3 species per lane the kernel fits 256 VGPRs (two wavefronts per SIMD, workgroups
-// of up to 8 wavefronts); larger states get 512 VGPRs (workgroups of up to 4 wavefronts).
-// In modes 3 and 4, up to 2 species per lane the kernel is built for 168 registers (three
-// wavefronts per SIMD, workgroups of up to 12 wavefronts).
-template <int NPL, int kMode>
-constexpr bool occ3() { return NPL <= 2 && kc_global(kMode); }
-template <int NPL, int kMode>
-constexpr int max_waves_per_wg() { return occ3<NPL, kMode>() ? 12 : NPL <= 3 ? 8 : 4; }
-template <int NPL, int kMode>
-constexpr int min_waves_per_simd() { return occ3<NPL, kMode>() ? 3 : 1; }
-int wave_max_waves(int n_state, int mode) {
+// One wavefront per cell (G = 64): up to 3 species per lane the kernel fits 256 VGPRs (two
+// wavefronts per SIMD, workgroups of up to 8 cells); larger states get 512 VGPRs
+// (workgroups of up to 4 cells). In modes 3 and 4, up to 2 species per lane the kernel is
+// built for 168 registers (three wavefronts per SIMD, workgroups of up to 12 cells).
+// One workgroup per cell (G = 128 or 256): at most 256 VGPRs (two wavefronts per SIMD).
+template <int NPL, int kMode, int G>
+constexpr bool occ3() { return G == kWave && NPL <= 2 && kc_global(kMode); }
+template <int NPL, int kMode, int G>
+constexpr int max_threads() {
+  return G > kWave ? G : kWave * (occ3<NPL, kMode, G>() ? 12 : NPL <= 3 ? 8 : 4);
+}
+template <int NPL, int kMode, int G>
+constexpr int min_waves_per_simd() { return G > kWave ? 2 : occ3<NPL, kMode, G>() ? 3 : 1; }
+
+int wave_lanes_ok(int n_state, int lanes) {
+  if (lanes == 64) return (n_state + 63) / 64 <= 9;
+  if (lanes == 128) return n_state > 64 && (n_state + 127) / 128 <= 5;
+  if (lanes == 256) return n_state > 128 && (n_state + 255) / 256 <= 3;
+  return 0;
+}
+
+int wave_max_waves(int n_state, int mode, int lanes) {
+  if (lanes != 64) return 1;
   const int npl = (n_state + kWave - 1) / kWave;
   return (npl <= 2 && kc_global(mode)) ? 12 : npl <= 3 ? 8 : 4;
 }
 
-// blockDim.x = 64 * W: W wavefronts, one cell each. queue != nullptr: persistent grid
-// pulling cells from the counter; else cell = blockIdx.x * W + wavefront. Mode 3 keeps the
-// rate constants at kc_glob + (blockIdx.x * W + wavefront) * R and needs the queue.
-template <int NPL, int kStage>
-__global__ __launch_bounds__((kWave * max_waves_per_wg<NPL, kStage>()),
-                             (min_waves_per_simd<NPL, kStage>())) void bdf_wave_kernel(
+int wave_resident_cells_per_cu(int n_state, int mode, int lanes) {
+  if (lanes == 64) return wave_max_waves(n_state, mode, 64);
+  return 8 / (lanes / 64);   // two wavefronts per SIMD, four SIMDs
+}
+
+// G = 64: blockDim.x = 64 * W, W wavefronts, one cell each; G > 64: blockDim.x = G, one
+// cell per workgroup. queue != nullptr: persistent grid pulling cells from the counter;
+// else cell = blockIdx.x * W + wavefront. Modes 3 and 4 keep the rate constants at
+// kc_glob + (blockIdx.x * W + wavefront) * R and need the queue.
+template <int NPL, int kStage, int G>
+__global__ __launch_bounds__((max_threads<NPL, kStage, G>()),
+                             (min_waves_per_simd<NPL, kStage, G>())) void bdf_wave_kernel(
     DevMech m, DevEnv env, double* state, int n_cells, SolveParams sp, int* status,
     camp_cell_stats* stats, int* queue, double* kc_glob) {
   extern __shared__ double lds[];
-  const Tabs tab = stage_tables<kStage>(m, lds);
-  const int W = blockDim.x / kWave, wid = threadIdx.x / kWave, lane = threadIdx.x % kWave;
-  double* base = lds + staged_bytes(m, kStage) / 8 + wid * cell_doubles(m, kStage);
+  const StageView& view = m.sv[G / 128];
+  const Tabs tab = stage_tables<kStage>(view, lds);
+  const int W = G == kWave ? blockDim.x / kWave : 1;
+  const int wid = G == kWave ? threadIdx.x / kWave : 0;
+  const int lane = threadIdx.x % G;
+  double* base = lds + staged_bytes(view, kStage) / 8 + wid * cell_doubles(m, kStage);
   const int np = m.n_part > m.R ? m.n_part : m.R;
-  double* kc = kc_global(kStage) ? kc_glob + (size_t)(blockIdx.x * W + wid) * m.R
-                                       : base + m.Z + 2 * m.N + np;
-  const WaveCell<NPL> Wc{m, tab, base, base + m.Z, base + m.Z + m.N, base + m.Z + 2 * m.N, kc, lane};
+  double* yl = base + m.Z;
+  double* xl = yl + m.N;
+  double* P = xl + m.N;
+  double* red = P + np;
+  double* kc = kc_global(kStage) ? kc_glob + (size_t)(blockIdx.x * W + wid) * m.R : red + 8;
+  const WaveCell<NPL, G> Wc{m, tab, base, yl, xl, P, kc, red, lane};
   if (!queue) {
     const int cell = blockIdx.x * W + wid;
-    if (cell < n_cells) solve_one_cell<NPL>(m, env, state, cell, sp, status, stats, Wc);
+    if (cell < n_cells) solve_one_cell<NPL, G>(m, env, state, cell, sp, status, stats, Wc);
     return;
   }
   while (true) {
     int cell = 0;
-    if (lane == 0) cell = atomicAdd(queue, 1);
-    cell = uniform(cell);
+    if constexpr (G == kWave) {
+      if (lane == 0) cell = atomicAdd(queue, 1);
+      cell = uniform(cell);
+    } else {
+      int* slot = reinterpret_cast<int*>(red + 4);
+      if (threadIdx.x == 0) *slot = atomicAdd(queue, 1);
+      __syncthreads();
+      cell = *slot;
+      __syncthreads();
+    }
     if (cell >= n_cells) break;
-    solve_one_cell<NPL>(m, env, state, cell, sp, status, stats, Wc);
+    solve_one_cell<NPL, G>(m, env, state, cell, sp, status, stats, Wc);
   }
 }
 
@@ -757,56 +874,94 @@ size_t wave_cell_bytes(const DevMech& m) { return sizeof(double) * cell_doubles(
 
 size_t wave_lds_bytes(const DevMech& m) { return wave_cell_bytes(m); }
 
-// LDS bytes of a workgroup of `waves` cells in launch mode `mode` (0..3).
-size_t wave_wg_lds_bytes(const DevMech& m, int waves, int mode) {
-  return (size_t)staged_bytes(m, mode) + (size_t)waves * sizeof(double) * cell_doubles(m, mode);
+// LDS bytes of a workgroup of `waves` cells in launch mode `mode` (0..4), with `lanes` per
+// cell (which picks the table layout).
+size_t wave_wg_lds_bytes(const DevMech& m, int waves, int mode, int lanes) {
+  return (size_t)staged_bytes(m.sv[lanes / 128], mode) +
+         (size_t)waves * sizeof(double) * cell_doubles(m, mode);
 }
 
-template <int NPL, int kStage>
+template <int NPL, int kStage, int G>
 hipError_t launch_wave_npl(const DevMech& m, const DevEnv& env, double* state, int n_cells,
                            const SolveParams& sp, int* status, camp_cell_stats* stats, int* queue,
                            double* kc_glob, int grid, int waves, size_t lds, hipStream_t stream) {
-  hipError_t e = hipFuncSetAttribute((const void*)bdf_wave_kernel<NPL, kStage>,
+  hipError_t e = hipFuncSetAttribute((const void*)bdf_wave_kernel<NPL, kStage, G>,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((bdf_wave_kernel<NPL, kStage>), dim3(grid), dim3(kWave * waves), lds, stream,
+  const int threads = G == kWave ? kWave * waves : G;
+  hipLaunchKernelGGL((bdf_wave_kernel<NPL, kStage, G>), dim3(grid), dim3(threads), lds, stream,
                      m, env, state, n_cells, sp, status, stats, queue, kc_glob);
   return hipGetLastError();
 }
 
-template <int NPL>
-hipError_t launch_wave_stage(const DevMech& m, const DevEnv& env, double* state, int n_cells,
-                             const SolveParams& sp, int* status, camp_cell_stats* stats,
-                             int* queue, double* kc_glob, int grid, int waves, int stage,
-                             size_t lds, hipStream_t stream) {
-  switch (stage) {
-    case 0: return launch_wave_npl<NPL, 0>(m, env, state, n_cells, sp, status, stats, queue, kc_glob, grid, waves, lds, stream);
-    case 1: return launch_wave_npl<NPL, 1>(m, env, state, n_cells, sp, status, stats, queue, kc_glob, grid, waves, lds, stream);
-    case 2: return launch_wave_npl<NPL, 2>(m, env, state, n_cells, sp, status, stats, queue, kc_glob, grid, waves, lds, stream);
-    case 3: return launch_wave_npl<NPL, 3>(m, env, state, n_cells, sp, status, stats, queue, kc_glob, grid, waves, lds, stream);
-    case 4: return launch_wave_npl<NPL, 4>(m, env, state, n_cells, sp, status, stats, queue, kc_glob, grid, waves, lds, stream);
-    default: return hipErrorInvalidValue;
+struct WaveLaunch {
+  const DevMech& m;
+  const DevEnv& env;
+  double* state;
+  int n_cells;
+  const SolveParams& sp;
+  int* status;
+  camp_cell_stats* stats;
+  int* queue;
+  double* kc_glob;
+  int grid, waves;
+  size_t lds;
+  hipStream_t stream;
+
+  template <int NPL, int G>
+  hipError_t run(int stage) const {
+    switch (stage) {
+      case 0: return launch_wave_npl<NPL, 0, G>(m, env, state, n_cells, sp, status, stats, queue, kc_glob, grid, waves, lds, stream);
+      case 1: return launch_wave_npl<NPL, 1, G>(m, env, state, n_cells, sp, status, stats, queue, kc_glob, grid, waves, lds, stream);
+      case 2: return launch_wave_npl<NPL, 2, G>(m, env, state, n_cells, sp, status, stats, queue, kc_glob, grid, waves, lds, stream);
+      case 3: return launch_wave_npl<NPL, 3, G>(m, env, state, n_cells, sp, status, stats, queue, kc_glob, grid, waves, lds, stream);
+      case 4: return launch_wave_npl<NPL, 4, G>(m, env, state, n_cells, sp, status, stats, queue, kc_glob, grid, waves, lds, stream);
+      default: return hipErrorInvalidValue;
+    }
   }
-}
+};
 
 hipError_t launch_bdf_wave(const DevMech& m, const DevEnv& env, double* state, int n_cells,
                            const SolveParams& sp, int* status, camp_cell_stats* stats, int* queue,
-                           double* kc_glob, int grid, int waves, int stage, hipStream_t stream) {
-  const size_t lds = wave_wg_lds_bytes(m, waves, stage);
-  const int npl = (m.N + kWave - 1) / kWave;
-  if (stage < 0 || stage > 4 || !m.stage) return hipErrorInvalidValue;
-  if (waves < 1 || waves > wave_max_waves(m.N, stage)) return hipErrorInvalidValue;
+                           double* kc_glob, int grid, int waves, int stage, int lanes,
+                           hipStream_t stream) {
+  if (!wave_lanes_ok(m.N, lanes)) return hipErrorInvalidValue;
+  if (stage < 0 || stage > 4) return hipErrorInvalidValue;
+  const StageView& view = m.sv[lanes / 128];
+  if (!view.base || view.wave_lists != lanes / kWave) return hipErrorInvalidValue;
+  if (waves < 1 || waves > wave_max_waves(m.N, stage, lanes)) return hipErrorInvalidValue;
   if (kc_global(stage) && (!queue || !kc_glob)) return hipErrorInvalidValue;
+  const WaveLaunch L{m, env, state, n_cells, sp, status, stats, queue, kc_glob, grid, waves,
+                     wave_wg_lds_bytes(m, waves, stage, lanes), stream};
+  const int npl = (m.N + lanes - 1) / lanes;
+  if (lanes == 64) {
+    switch (npl) {
+      case 1: return L.run<1, 64>(stage);
+      case 2: return L.run<2, 64>(stage);
+      case 3: return L.run<3, 64>(stage);
+      case 4: return L.run<4, 64>(stage);
+      case 5: return L.run<5, 64>(stage);
+      case 6: return L.run<6, 64>(stage);
+      case 7: return L.run<7, 64>(stage);
+      case 8: return L.run<8, 64>(stage);
+      case 9: return L.run<9, 64>(stage);
+      default: return hipErrorInvalidValue;
+    }
+  }
+  if (lanes == 128) {
+    switch (npl) {
+      case 1: return L.run<1, 128>(stage);
+      case 2: return L.run<2, 128>(stage);
+      case 3: return L.run<3, 128>(stage);
+      case 4: return L.run<4, 128>(stage);
+      case 5: return L.run<5, 128>(stage);
+      default: return hipErrorInvalidValue;
+    }
+  }
   switch (npl) {
-    case 1: return launch_wave_stage<1>(m, env, state, n_cells, sp, status, stats, queue, kc_glob, grid, waves, stage, lds, stream);
-    case 2: return launch_wave_stage<2>(m, env, state, n_cells, sp, status, stats, queue, kc_glob, grid, waves, stage, lds, stream);
-    case 3: return launch_wave_stage<3>(m, env, state, n_cells, sp, status, stats, queue, kc_glob, grid, waves, stage, lds, stream);
-    case 4: return launch_wave_stage<4>(m, env, state, n_cells, sp, status, stats, queue, kc_glob, grid, waves, stage, lds, stream);
-    case 5: return launch_wave_stage<5>(m, env, state, n_cells, sp, status, stats, queue, kc_glob, grid, waves, stage, lds, stream);
-    case 6: return launch_wave_stage<6>(m, env, state, n_cells, sp, status, stats, queue, kc_glob, grid, waves, stage, lds, stream);
-    case 7: return launch_wave_stage<7>(m, env, state, n_cells, sp, status, stats, queue, kc_glob, grid, waves, stage, lds, stream);
-    case 8: return launch_wave_stage<8>(m, env, state, n_cells, sp, status, stats, queue, kc_glob, grid, waves, stage, lds, stream);
-    case 9: return launch_wave_stage<9>(m, env, state, n_cells, sp, status, stats, queue, kc_glob, grid, waves, stage, lds, stream);
+    case 1: return L.run<1, 256>(stage);
+    case 2: return L.run<2, 256>(stage);
+    case 3: return L.run<3, 256>(stage);
     default: return hipErrorInvalidValue;
   }
 }
@@ -821,10 +976,12 @@ __global__ __launch_bounds__(kWave) void wave_step_kernel(DevMech m, int op, int
                                                           double* out, double gamma) {
   extern __shared__ double lds[];
   const int np = m.n_part > m.R ? m.n_part : m.R;
-  const char* g = reinterpret_cast<const char*>(m.stage);
-  const WaveCell<NPL> W{m, Tabs{g, g, m}, lds, lds + m.Z,
-                        lds + m.Z + m.N, lds + m.Z + 2 * m.N, lds + m.Z + 2 * m.N + np,
-                        (int)threadIdx.x};
+  const char* g = reinterpret_cast<const char*>(m.sv[0].base);
+  double* yl = lds + m.Z;
+  double* xl = yl + m.N;
+  double* P = xl + m.N;
+  const WaveCell<NPL, kWave> W{m, Tabs{g, g, m.sv[0]}, lds, yl, xl, P, P + np + 8, P + np,
+                               (int)threadIdx.x};
   const int cell = blockIdx.x;
   if (cell >= n_cells) return;
   const int lane = threadIdx.x;

@@ -105,15 +105,19 @@ struct Compiled {
 //   forward:     x[dst] -= M[slot] * x[src] (unit lower)
 //   diagonal:    x[t] *= M[diag[t]]
 //   backward:    x[dst] -= M[slot] * x[src] (row-scaled upper, unit diagonal)
-// Layout: rx u32 [R]; diag u16 [N]; sf/sb terms uint2 {dst | src << 16, slot} with level
-// pointers u32; LU terms uint2 {dst | pa << 16, pb} with level pointers u32 [levels + 1];
-// finalize u32 {dst | piv << 16} (piv 0xFFFF: invert) with pointers u32 [levels + 2];
-// row scaling u32 {slot | piv << 16}.
+// Layout: rx u32 [R]; diag u16 [N]; sf/sb terms uint2 {dst | src << 16, slot}; LU terms
+// uint2 {dst | pa << 16, pb}; finalize u32 {dst | piv << 16} (piv 0xFFFF: invert) with
+// pointers u32 [levels + 2]; row scaling u32 {slot | piv << 16}.
+// The product terms of each level (and the forcing / Jacobian lists) are stored as W
+// per-wavefront lists (W = wave_lists: 1 for one wavefront per cell, 2 or 4 for a
+// workgroup per cell); all terms of one destination are in one list, so the order in
+// which they accumulate is fixed. Pointers u32 [W * levels + 1]: list a of level l spans
+// [ptr[W l + a], ptr[W l + a + 1]).
 // The block has a core part (the above) followed by an extension with the forcing terms
 // (u32 {species | reaction << 16}, coef f64) and the Jacobian contributions
-// (u32 {slot | partial << 16}, coef f64) as flat lists, so a workgroup may stage only the
-// core when the whole block does not fit. Terms of every list are interleaved by
-// destination (see interleave_by_dst).
+// (u32 {slot | partial << 16}, coef f64), W lists each with pointers u32 [W + 1], so a
+// workgroup may stage only the core when the whole block does not fit. Every list is
+// interleaved by destination (see interleave_by_dst).
 struct StageBlock {
   std::vector<uint8_t> bytes;
   int core_bytes = 0;
@@ -122,10 +126,14 @@ struct StageBlock {
   int off_lt = 0, off_lt_lp = 0, off_lf = 0, off_lf_lp = 0, off_us = 0;
   int n_sf_lev = 0, n_sb_lev = 0, n_us = 0;
   int off_ft = 0, off_ft_coef = 0, off_jt = 0, off_jt_coef = 0, n_ft = 0, n_jt = 0;
+  int off_ft_lp = 0, off_jt_lp = 0;
+  int wave_lists = 1;
   bool ok = false;   // false when the mechanism exceeds the 16-bit index ranges
 };
 
-StageBlock build_stage_block(const Compiled& C);
+// wave_lists: per-wavefront term lists per level, 1 (one wavefront per cell), 2 or 4 (one
+// workgroup of that many wavefronts per cell).
+StageBlock build_stage_block(const Compiled& C, int wave_lists);
 
 // Returns an empty string on success, else the validation/compile error.
 std::string compile_mechanism(const camp_reaction* rxns, int n_rxn, const camp_species* sp,

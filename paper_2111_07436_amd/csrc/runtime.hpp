@@ -22,6 +22,8 @@ struct Tuning {
   int persistent = 1;        // wave engine: 1 = queue-driven persistent grid
   int grid_mult = 8;         // wave engine: workgroups per CU when persistent
   int waves = 1;             // wave engine: wavefronts (cells) per workgroup
+  int lanes = 64;            // wave engine: lanes per cell (64: one wavefront; 128, 256: a
+                             // whole workgroup per cell)
   int stage = 1;             // wave engine launch mode: tables staged in LDS (0 none, 1 index,
                              // 2 all); 3 / 4 as 0 / 1 with rate constants in global scratch
   double ms = 0.0;           // measured trial time
@@ -40,11 +42,14 @@ int hip_fail(hipError_t e, const char* what);
 // Launchers (defined in the engine files).
 size_t wave_lds_bytes(const DevMech& m);
 size_t wave_cell_bytes(const DevMech& m);
-size_t wave_wg_lds_bytes(const DevMech& m, int waves, int stage);
-int wave_max_waves(int n_state, int mode);
+size_t wave_wg_lds_bytes(const DevMech& m, int waves, int stage, int lanes);
+int wave_max_waves(int n_state, int mode, int lanes);
+int wave_lanes_ok(int n_state, int lanes);
+int wave_resident_cells_per_cu(int n_state, int mode, int lanes);
 hipError_t launch_bdf_wave(const DevMech& m, const DevEnv& env, double* state, int n_cells,
                            const SolveParams& sp, int* status, camp_cell_stats* stats, int* queue,
-                           double* kc_glob, int grid, int waves, int stage, hipStream_t stream);
+                           double* kc_glob, int grid, int waves, int stage, int lanes,
+                           hipStream_t stream);
 constexpr size_t kLdsBytes = 160 * 1024;
 hipError_t launch_wave_step(const DevMech& m, int op, int n_cells, const double* kin,
                             const double* yin, double* out, double gamma, hipStream_t stream);
@@ -63,7 +68,7 @@ hipError_t launch_fill_int(int* p, int n, int v, hipStream_t stream);
 
 struct camp_mech {
   camp::Compiled C;
-  camp::StageBlock stage;
+  camp::StageBlock stage[3];   // term lists for 1, 2 and 4 wavefronts per cell
   std::mutex mu;
   std::map<int, camp::DeviceTables> dev;            // per device id
   std::map<std::pair<int, int>, camp::Tuning> tune; // (device, cell bucket)

@@ -199,6 +199,28 @@ def test_launch_modes_bit_identical(torch):
                 assert np.array_equal(y, ref), (name, mode, waves)
 
 
+@pytest.mark.parametrize("lanes", [128, 256])
+def test_workgroup_per_cell_parity(torch, lanes):
+    """One workgroup of 2 or 4 wavefronts per cell (group-wide reductions and barriers):
+    same gate against the oracle, and bit-identical across launch modes."""
+    from paper_2111_07436_amd import camp
+    wl = W.make_workload("c3", n_cells=70)
+    m = camp.Mech(wl.mech)
+    ref = None
+    for mode in (0, 1, 3):
+        log(f"c3 lanes {lanes} mode {mode}")
+        y = gpu_solve(m, wl, "wave", lanes_per_cell=lanes, stage_tables=mode, persistent=1, wg_per_cu=2)
+        if ref is None:
+            ref = y
+        assert np.array_equal(y, ref), mode
+    sample = [0, 1, 33, 69]
+    yr, st, _ = oracle_solve(wl.mech, wl.env, wl.y0, wl.dt, 1, OR_RTOL, OR_ATOL, cells=sample)
+    assert np.all(st == 0)
+    assert_parity(ref[sample], yr, what=f"c3/lanes {lanes}")
+    y = gpu_solve(m, wl, "wave", lanes_per_cell=lanes, persistent=0)
+    assert np.array_equal(y, ref)
+
+
 def test_plain_graph_replay_identical(torch):
     """The plain multi-kernel form replays a captured chunk of step-attempt launches; the
     states equal those of direct launches."""
@@ -259,7 +281,8 @@ def test_c5_sample_against_stored_oracle(torch):
     sub = wl.take(cells)
     m = camp.Mech(sub.mech)
     for kw in ({"engine": "wave", "stage_tables": 0}, {"engine": "wave", "stage_tables": 3},
-               {"engine": "lane"}):
+               {"engine": "wave", "stage_tables": 3, "lanes_per_cell": 128},
+               {"engine": "wave", "stage_tables": 3, "lanes_per_cell": 256}, {"engine": "lane"}):
         log(f"c5 sample: {len(cells)} cells, {kw}")
         y = gpu_solve(m, sub, **kw)
         assert_parity(y, np.asarray(g["y"])[ok], what=f"c5/{kw}")
