@@ -29,7 +29,7 @@ HBM_PEAK_GBS = 8000.0
 # WRITE_SIZE runs of this script (KiB per dispatch), each scaled by the ratio of the known
 # size to the counter's reading for a plain device copy (`--calibrate-copy`). Valid only
 # for the kernel sources it was taken with (their SHA-256 prefix); otherwise reported null.
-KERNEL_SOURCES = ["paper_2111_07436_amd/csrc/engine_wave.hip", "paper_2111_07436_amd/csrc/device.hpp",
+KERNEL_SOURCES = ["paper_2111_07436_amd/csrc/engine_wave.hpp", "paper_2111_07436_amd/csrc/device.hpp",
                   "paper_2111_07436_amd/csrc/bdf_common.hpp"]
 MEASURED_TRAFFIC = {
     # bdf_wave_kernel<2, 2>, 131072 x 512 persistent launch (autotuned), mean of the timed launches

@@ -1,811 +1,9 @@
-// Fused persistent engine, one wavefront per cell.
-//
-// Every cell's whole integration over the host step (rate constants, then BDF steps with
-// forcing, Newton matrix, sparse LU and triangular solves, error test and step/order
-// control) runs inside one kernel. A wavefront owns one cell at a time: its Newton matrix,
-// state, right-hand side, rates and partial derivatives live in LDS, and its BDF history
-// lives in registers with species t held by lane t % 64. Sparse work is spread over the
-// 64 lanes by the level-scheduled tables built on the host: every task of one dependency
-// level runs in parallel, levels are separated by a wavefront-scoped barrier. Control
-// decisions use wavefront reductions, so they are uniform and need no masking.
-//
-// A workgroup holds several wavefronts (cells) that share one LDS copy of the
-// latency-critical index tables (reactants, CSR pattern with level-ordered solve rows,
-// Crout LU tasks and pairs), staged once per workgroup. When a cell is done the wavefront
-// takes the next one from a device-side queue (persistent grid) or from the grid index.
-//
-// Forcing and Jacobian (paper Sect. 2.4.2): f_i = sum_k S_ik r_k and
-// J_ij = sum_k S_ik dr_k/dy_j, with r_k = k_k prod y over reactant occurrences.
-#include "bdf_common.hpp"
-#include "camp.h"
+// Fused persistent engine, host side: launch shapes, LDS sizes and the dispatch of a launch
+// to the kernel instantiation for its species per lane, group size and launch mode; and the
+// single-step kernels behind the step entry points.
+#include "engine_wave.hpp"
 
 namespace camp {
-
-namespace {
-
-// Orders LDS traffic of one wavefront: LDS instructions of a wavefront execute in order,
-// so a release/acquire fence at wavefront scope is all that lanes need to see each
-// other's writes.
-__device__ __forceinline__ void wave_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
-// Wavefront-uniform copy of a value every lane holds.
-__device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
-
-// LDS accumulation: several lanes of one instruction may target the same entry.
-__device__ __forceinline__ void lds_add(double* p, double v) {
-  __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
-}
-
-// The lanes that integrate one cell: one wavefront (G = 64, several cells per workgroup),
-// or a whole workgroup of G / 64 wavefronts (G = 128 or 256, one cell per workgroup).
-// Control decisions come from group-wide reductions, so every lane of the group takes the
-// same path.
-template <int G>
-struct Group {
-  static_assert(G == 64 || G == 128 || G == 256, "lanes per cell");
-  static constexpr int kWaves = G / kWave;
-  // Orders the LDS (and global scratch) traffic of the group's lanes.
-  __device__ static void sync() {
-    if constexpr (G == kWave) wave_sync();
-    else __syncthreads();
-  }
-  // Sum over the group, the same value in every lane. red: kWaves doubles of LDS.
-  __device__ static double sum(double v, double* red) {
-    v = wave_sum(v);
-    if constexpr (G == kWave) {
-      return v;
-    } else {
-      if (threadIdx.x % kWave == 0) red[threadIdx.x / kWave] = v;
-      __syncthreads();
-      double t = red[0];
-#pragma unroll
-      for (int k = 1; k < kWaves; ++k) t += red[k];
-      __syncthreads();
-      return t;
-    }
-  }
-  // Nonzero in any lane of the group.
-  __device__ static int any(int v, double* red) {
-    const int a = wave_or(v);
-    if constexpr (G == kWave) {
-      return a;
-    } else {
-      if (threadIdx.x % kWave == 0) red[threadIdx.x / kWave] = a ? 1.0 : 0.0;
-      __syncthreads();
-      double t = 0.0;
-#pragma unroll
-      for (int k = 0; k < kWaves; ++k) t += red[k];
-      __syncthreads();
-      return t != 0.0;
-    }
-  }
-};
-
-// One update of a term loop: add `v` to entry `dst`.
-struct TermUpdate {
-  int dst;
-  double v;
-};
-
-// Runs the terms i = lo + lane, lo + lane + G, ... < hi of a term list (G lanes) in groups
-// of kU: the loads of a group (gather) are all issued before any of its updates (scatter),
-// so their latencies overlap. Only valid where no term of the list reads what another
-// writes.
-template <int kU, int G, class Gather, class Scatter>
-__device__ __forceinline__ void for_terms(int lo, int hi, int lane, Gather gather, Scatter scatter) {
-  int i = lo + lane;
-  for (; i + (kU - 1) * G < hi; i += kU * G) {
-    TermUpdate it[kU];
-#pragma unroll
-    for (int u = 0; u < kU; ++u) it[u] = gather(i + u * G);
-#pragma unroll
-    for (int u = 0; u < kU; ++u) scatter(it[u]);
-  }
-  for (; i < hi; i += G) scatter(gather(i));
-}
-
-constexpr int kTermBatch = 4;
-
-// Level pointers of a term list held in registers: lane k holds entry k and entry k + 64,
-// so reading the bounds of a level is a lane read instead of an LDS round trip. Lists of
-// more than 127 levels read the rest from the table.
-struct LevelPtrs {
-  int a, b;
-};
-
-// Loads entries 0..nlev of a level-pointer table (ptr(l) reads entry l); entry 0 is 0.
-template <class Ptr>
-__device__ __forceinline__ LevelPtrs load_levels(int nlev, Ptr ptr) {
-  const int lane = threadIdx.x % kWave;
-  LevelPtrs p{0, 0};
-  if (lane <= nlev) p.a = ptr(lane);
-  if (lane + kWave <= nlev) p.b = ptr(lane + kWave);
-  return p;
-}
-
-template <class Ptr>
-__device__ __forceinline__ int level_ptr(const LevelPtrs& p, int l, Ptr ptr) {
-  if (l < kWave) return __builtin_amdgcn_readlane(p.a, l);
-  if (l < 2 * kWave) return __builtin_amdgcn_readlane(p.b, l - kWave);
-  return uniform(ptr(l));
-}
-
-// Bounds of one wavefront's term list in each level of a table with kW lists per level
-// (list a of level l spans [ptr(kW l + a), ptr(kW l + a + 1))), held in registers like
-// LevelPtrs: lane k holds the bounds of levels k and k + 64.
-struct LevelRange {
-  int s0, e0, s1, e1;
-};
-
-template <int kW, class Ptr>
-__device__ __forceinline__ LevelRange load_ranges(int nlev, int wid, Ptr ptr) {
-  const int l = threadIdx.x % kWave;
-  LevelRange r{0, 0, 0, 0};
-  if (l < nlev) {
-    r.s0 = ptr(kW * l + wid);
-    r.e0 = ptr(kW * l + wid + 1);
-  }
-  if (l + kWave < nlev) {
-    r.s1 = ptr(kW * (l + kWave) + wid);
-    r.e1 = ptr(kW * (l + kWave) + wid + 1);
-  }
-  return r;
-}
-
-template <int kW, class Ptr>
-__device__ __forceinline__ int2 level_range(const LevelRange& r, int l, int wid, Ptr ptr) {
-  if (l < kWave)
-    return make_int2(__builtin_amdgcn_readlane(r.s0, l), __builtin_amdgcn_readlane(r.e0, l));
-  if (l < 2 * kWave)
-    return make_int2(__builtin_amdgcn_readlane(r.s1, l - kWave),
-                     __builtin_amdgcn_readlane(r.e1, l - kWave));
-  return make_int2(uniform(ptr(kW * l + wid)), uniform(ptr(kW * l + wid + 1)));
-}
-
-// Accessors of the compact table block: the core tables through `b`, the forcing-term and
-// Jacobian-contribution extension through `e`; each base is LDS (staged) or global memory.
-struct Tabs {
-  const char* b;
-  const char* e;
-  const StageView& v;
-  __device__ uint32_t ft(int i) const { return reinterpret_cast<const uint32_t*>(e + v.so_ft)[i]; }
-  __device__ double ft_coef(int i) const { return reinterpret_cast<const double*>(e + v.so_ft_coef)[i]; }
-  __device__ uint32_t jt(int i) const { return reinterpret_cast<const uint32_t*>(e + v.so_jt)[i]; }
-  __device__ int ft_lp(int a) const { return (int)reinterpret_cast<const uint32_t*>(e + v.so_ft_lp)[a]; }
-  __device__ int jt_lp(int a) const { return (int)reinterpret_cast<const uint32_t*>(e + v.so_jt_lp)[a]; }
-  __device__ double jt_coef(int i) const { return reinterpret_cast<const double*>(e + v.so_jt_coef)[i]; }
-  __device__ uint32_t rx(int k) const { return reinterpret_cast<const uint32_t*>(b + v.so_rx)[k]; }
-  __device__ int dg(int t) const { return reinterpret_cast<const uint16_t*>(b + v.so_diag)[t]; }
-  __device__ uint2 sf(int i) const { return reinterpret_cast<const uint2*>(b + v.so_sf)[i]; }
-  __device__ int sf_lp(int l) const { return (int)reinterpret_cast<const uint32_t*>(b + v.so_sf_lp)[l]; }
-  __device__ uint2 sb(int i) const { return reinterpret_cast<const uint2*>(b + v.so_sb)[i]; }
-  __device__ int sb_lp(int l) const { return (int)reinterpret_cast<const uint32_t*>(b + v.so_sb_lp)[l]; }
-  __device__ uint2 lt(int i) const { return reinterpret_cast<const uint2*>(b + v.so_lt)[i]; }
-  __device__ int lt_lp(int l) const { return (int)reinterpret_cast<const uint32_t*>(b + v.so_lt_lp)[l]; }
-  __device__ uint32_t lf(int i) const { return reinterpret_cast<const uint32_t*>(b + v.so_lf)[i]; }
-  __device__ int lf_lp(int l) const { return (int)reinterpret_cast<const uint32_t*>(b + v.so_lf_lp)[l]; }
-  __device__ uint32_t us(int i) const { return reinterpret_cast<const uint32_t*>(b + v.so_us)[i]; }
-};
-
-template <int NPL, int G>
-struct WaveCell {
-  // Terms per lane issued together in the LU and sweep levels: levels of large mechanisms
-  // hold several terms per lane, small ones rarely more than one.
-  static constexpr int kLevelBatch = NPL >= 4 ? 4 : 1;
-  const DevMech& m;
-  Tabs tb;
-  double* M;
-  double* yl;
-  double* xl;
-  double* P;
-  double* kc;
-  double* red;   // reduction scratch of the group (8 doubles of LDS)
-  int lane;      // 0 .. G-1
-  static constexpr int kW = G / kWave;   // wavefronts per cell = term lists per level
-  __device__ static int wlane() { return threadIdx.x % kWave; }
-  __device__ static int wid() { return (threadIdx.x % G) / kWave; }
-
-  __device__ void sync() const { Group<G>::sync(); }
-  __device__ int any(int v) const { return Group<G>::any(v, red); }
-
-  __device__ double wrms(const double (&v)[NPL], const double (&w)[NPL]) const {
-    double s = 0.0;
-#pragma unroll
-    for (int i = 0; i < NPL; ++i)
-      if (lane + G * i < m.N) {
-        double a = v[i] * w[i];
-        s += a * a;
-      }
-    return sqrt(Group<G>::sum(s, red) / m.N);
-  }
-
-  // P[k] = r_k from yl; then f for owned species, accumulated term by term (one term per
-  // lane) in xl, which no caller holds live across this call. yl must be visible to all
-  // lanes.
-  __device__ void forcing(double (&f)[NPL]) const {
-    for (int k = lane; k < m.R; k += G) {
-      const uint32_t v = tb.rx(k);
-      const int a = v & 0x3FF, b = (v >> 10) & 0x3FF, c = (v >> 20) & 0x3FF;
-      double r = kc[k];
-      if (a != 0x3FF) r *= yl[a];
-      if (b != 0x3FF) r *= yl[b];
-      if (c != 0x3FF) r *= yl[c];
-      P[k] = r;
-    }
-    for (int t = lane; t < m.N; t += G) xl[t] = 0.0;
-    sync();
-    for_terms<kTermBatch, kWave>(
-        uniform(tb.ft_lp(wid())), uniform(tb.ft_lp(wid() + 1)), wlane(),
-        [&](int i) {
-          const uint32_t e = tb.ft(i);
-          return TermUpdate{(int)(e & 0xFFFF), tb.ft_coef(i) * P[e >> 16]};
-        },
-        [&](const TermUpdate& u) { lds_add(&xl[u.dst], u.v); });
-    sync();
-#pragma unroll
-    for (int i = 0; i < NPL; ++i) {
-      const int t = lane + G * i;
-      f[i] = t < m.N ? xl[t] : 0.0;
-    }
-    sync();
-  }
-
-  // M = I - c J(yl) in the filled pattern (fill slots 0 off the diagonal), accumulated
-  // contribution by contribution (one per lane).
-  __device__ void newton_matrix(double c) const {
-    for (int k = lane; k < m.R; k += G) {
-      const uint32_t v = tb.rx(k);
-      const int a = v & 0x3FF, b = (v >> 10) & 0x3FF, cc = (v >> 20) & 0x3FF;
-      const double kk = kc[k];
-      const int base = m.rx_pofs[k];
-      const double ya = a != 0x3FF ? yl[a] : 1.0, yb = b != 0x3FF ? yl[b] : 1.0,
-                   yc = cc != 0x3FF ? yl[cc] : 1.0;
-      if (a != 0x3FF) P[base] = kk * yb * yc;
-      if (b != 0x3FF) P[base + 1] = kk * ya * yc;
-      if (cc != 0x3FF) P[base + 2] = kk * ya * yb;
-    }
-    for (int s = lane; s < m.Z; s += G) M[s] = 0.0;
-    sync();
-    const double mc = -c;
-    for_terms<kTermBatch, kWave>(
-        uniform(tb.jt_lp(wid())), uniform(tb.jt_lp(wid() + 1)), wlane(),
-        [&](int i) {
-          const uint32_t e = tb.jt(i);
-          return TermUpdate{(int)(e & 0xFFFF), mc * tb.jt_coef(i) * P[e >> 16]};
-        },
-        [&](const TermUpdate& u) { lds_add(&M[u.dst], u.v); });
-    sync();
-    for (int t = lane; t < m.N; t += G) M[tb.dg(t)] += 1.0;
-    sync();
-  }
-
-  // In-place Crout LU of M, one dependency level at a time: the level's product terms in
-  // parallel (one per lane), then its finalize entries (L entries times the reciprocal
-  // pivot, pivots inverted). Leaves the unit-diagonal factors: L strictly below the
-  // diagonal, reciprocal pivots on it, and U / diag(U) strictly above. Returns 0 if a
-  // pivot is not a finite nonzero.
-  __device__ int lu() const {
-    const int L = m.lu_levels;
-    auto ltp = [&](int k) { return tb.lt_lp(k); };
-    const LevelRange tr = load_ranges<kW>(L, wid(), ltp);
-    const LevelPtrs fp = load_levels(L + 1, [&](int l) { return tb.lf_lp(l); });
-    int fhi = level_ptr(fp, 1, [&](int l) { return tb.lf_lp(l); });
-    for (int i = lane; i < fhi; i += G) {
-      const int d = tb.lf(i) & 0xFFFF;
-      M[d] = 1.0 / M[d];
-    }
-    sync();
-    for (int l = 0; l < L; ++l) {
-      const int2 r = level_range<kW>(tr, l, wid(), ltp);
-      for_terms<kLevelBatch, kWave>(
-          r.x, r.y, wlane(),
-          [&](int i) {
-            const uint2 e = tb.lt(i);
-            return TermUpdate{(int)(e.x & 0xFFFF), M[e.x >> 16] * M[e.y]};
-          },
-          [&](const TermUpdate& u) { lds_add(&M[u.dst], -u.v); });
-      sync();
-      const int flo = fhi;
-      fhi = level_ptr(fp, l + 2, [&](int k) { return tb.lf_lp(k); });
-      if (flo == fhi) continue;
-      for (int i = flo + lane; i < fhi; i += G) {
-        const uint32_t e = tb.lf(i);
-        const int dst = e & 0xFFFF, pv = e >> 16;
-        M[dst] = pv == 0xFFFF ? 1.0 / M[dst] : M[dst] * M[pv];
-      }
-      sync();
-    }
-    for (int i = lane; i < tb.v.n_us; i += G) {
-      const uint32_t e = tb.us(i);
-      M[e & 0xFFFF] *= M[e >> 16];
-    }
-    int bad = 0;
-    for (int t = lane; t < m.N; t += G) {
-      const double r = M[tb.dg(t)];
-      if (!(fabs(r) > 0.0) || !isfinite(r)) bad = 1;
-    }
-    sync();
-    return !any(bad);
-  }
-
-  __device__ int newton_matrix_lu(double c) const {
-    newton_matrix(c);
-    return lu();
-  }
-
-  // Conversions between the factor form lu() leaves and the conventional one (unit L
-  // strictly below the diagonal, U on and above it).
-  __device__ void factors_to_conventional() const {
-    for (int i = lane; i < tb.v.n_us; i += G) {
-      const uint32_t e = tb.us(i);
-      M[e & 0xFFFF] /= M[e >> 16];
-    }
-    sync();
-    for (int t = lane; t < m.N; t += G) M[tb.dg(t)] = 1.0 / M[tb.dg(t)];
-    sync();
-  }
-  __device__ void factors_from_conventional() const {
-    for (int t = lane; t < m.N; t += G) M[tb.dg(t)] = 1.0 / M[tb.dg(t)];
-    sync();
-    for (int i = lane; i < tb.v.n_us; i += G) {
-      const uint32_t e = tb.us(i);
-      M[e & 0xFFFF] *= M[e >> 16];
-    }
-    sync();
-  }
-
-  // One triangular sweep over the unit-diagonal factor: x[dst] -= M[slot] * x[src] for
-  // the terms of each level, one term per lane.
-  template <bool kForward>
-  __device__ void sweep() const {
-    const int nlev = kForward ? tb.v.n_sf_lev : tb.v.n_sb_lev;
-    auto lp = [&](int l) { return kForward ? tb.sf_lp(l) : tb.sb_lp(l); };
-    const LevelRange p = load_ranges<kW>(nlev, wid(), lp);
-    for (int l = 0; l < nlev; ++l) {
-      const int2 r = level_range<kW>(p, l, wid(), lp);
-      for_terms<kLevelBatch, kWave>(
-          r.x, r.y, wlane(),
-          [&](int i) {
-            const uint2 e = kForward ? tb.sf(i) : tb.sb(i);
-            return TermUpdate{(int)(e.x & 0xFFFF), M[e.y] * xl[e.x >> 16]};
-          },
-          [&](const TermUpdate& u) { lds_add(&xl[u.dst], -u.v); });
-      sync();
-    }
-  }
-
-  // xl <- (LU)^-1 xl from the factors lu() leaves: forward sweep, diagonal scaling,
-  // backward sweep.
-  __device__ void solve() const {
-    sweep<true>();
-    for (int t = lane; t < m.N; t += G) xl[t] *= M[tb.dg(t)];
-    sync();
-    sweep<false>();
-  }
-};
-
-// Step change by rho: D[1..q] become the backward differences at the new spacing of the
-// polynomial interpolating the history (rescale_point / rescale_differences).
-template <int NPL>
-__device__ __forceinline__ void rescale_hist(double (&D)[kHist][NPL], int q, double rho) {
-#pragma unroll
-  for (int i = 0; i < NPL; ++i) {
-    double a[kMaxOrder + 1];
-#pragma unroll
-    for (int mm = 0; mm <= kMaxOrder; ++mm) {
-      double acc = 0.0;
-#pragma unroll
-      for (int k = kMaxOrder; k >= 1; --k)
-        if (k <= q) acc = rescale_coef(k, mm, rho) * (D[k][i] + acc);
-      a[mm] = D[0][i] + acc;
-    }
-#pragma unroll
-    for (int lev = 1; lev <= kMaxOrder; ++lev) {
-#pragma unroll
-      for (int mm = 0; mm + lev <= kMaxOrder; ++mm) a[mm] -= a[mm + 1];
-      if (lev <= q) D[lev][i] = a[0];
-    }
-  }
-}
-
-// Integrates one cell over the host step from its input row (rate constants already in
-// LDS; `bad` flags a non-finite rate constant on this lane). full != 0: full Newton, with a
-// fresh Jacobian and LU at every iteration; else Newton with Jacobian reuse. On success
-// the state row is overwritten; on failure it is left as it was.
-template <int NPL, int G>
-__device__ __forceinline__ int integrate(const DevMech& m, double* yrow, const SolveParams& sp, int bad, int full,
-                         camp_cell_stats& cs, const WaveCell<NPL, G>& W) {
-  const int lane = W.lane;
-  const int N = m.N;
-  int status = ST_OK;
-
-  // ---- initial state ----
-  double D[kHist][NPL];
-#pragma unroll
-  for (int i = 0; i < NPL; ++i) {
-    const int t = lane + G * i;
-    const double v = t < N ? yrow[m.perm[t]] : 0.0;
-    if (t < N) {
-      W.yl[t] = v;
-      if (!isfinite(v)) bad = 1;
-    }
-    D[0][i] = v;
-#pragma unroll
-    for (int j = 1; j < kHist; ++j) D[j][i] = 0.0;
-  }
-  W.sync();
-  if (W.any(bad)) status = ST_NONFINITE;
-
-  const double span = sp.dt;
-  double w[NPL], f0[NPL], d[NPL];
-  if (status == ST_OK) {
-    W.forcing(f0);
-    cs.n_f++;
-    int nf = 0;
-#pragma unroll
-    for (int i = 0; i < NPL; ++i) {
-      if (!isfinite(f0[i])) nf = 1;
-      const double s = sp.atol + sp.rtol * fabs(D[0][i]);
-      w[i] = s > 0.0 ? 1.0 / s : 0.0;
-    }
-    if (W.any(nf)) status = ST_NONFINITE;
-  }
-  double h = 0.0;
-  if (status == ST_OK) {
-    // starting step
-    const double d0 = W.wrms(D[0], w), d1 = W.wrms(f0, w);
-    const double h0 = starting_step_h0(d0, d1, span);
-#pragma unroll
-    for (int i = 0; i < NPL; ++i) {
-      const int t = lane + G * i;
-      if (t < N) W.yl[t] = D[0][i] + h0 * f0[i];
-    }
-    W.sync();
-    double f1[NPL];
-    W.forcing(f1);
-    cs.n_f++;
-#pragma unroll
-    for (int i = 0; i < NPL; ++i) f1[i] -= f0[i];
-    const double d2 = W.wrms(f1, w) / h0;
-    h = sp.h_init > 0.0 ? fmin(sp.h_init, span) : starting_step(h0, d1, d2, span);
-#pragma unroll
-    for (int i = 0; i < NPL; ++i) D[1][i] = h * f0[i];
-  }
-
-  int q = 1, n_equal = 0, attempts = 0, lu_valid = 0, lu_age = 0;
-  double t = 0.0, c_lu = 0.0, crate = 1.0, err = 0.0;
-  while (status == ST_OK && t < span) {
-    if (span - (t + h) <= 1e-12 * span) {
-      const double rho = (span - t) / h;
-      if (rho != 1.0) {
-        rescale_hist(D, q, rho);
-        h = span - t;
-        n_equal = 0;
-      }
-    }
-    int nfw = 0;
-#pragma unroll
-    for (int i = 0; i < NPL; ++i) {
-      w[i] = 1.0 / (sp.rtol * fabs(D[0][i]) + sp.atol);
-      if (lane + G * i < N && !isfinite(w[i])) nfw = 1;
-    }
-    if (W.any(nfw)) {
-      status = ST_NONFINITE;
-      break;
-    }
-    int consec_err = 0, consec_nf = 0, force_lu = 0;
-    bool accepted = false;
-    while (true) {
-      if (++attempts > sp.max_steps) { status = ST_MAX_STEPS; break; }
-      if (h < sp.h_min) { status = ST_H_MIN; break; }
-      const double gq = bdf_gamma(q);
-      const double c = h / gq;
-      double psi[NPL], yv[NPL];
-#pragma unroll
-      for (int i = 0; i < NPL; ++i) {
-        double s = D[0][i], ps = 0.0, g = 0.0;
-#pragma unroll
-        for (int j = 1; j <= kMaxOrder; ++j) {
-          g += 1.0 / j;
-          if (j <= q) {
-            s += D[j][i];
-            ps += g * D[j][i];
-          }
-        }
-        psi[i] = ps / gq;
-        yv[i] = s;
-        d[i] = 0.0;
-        const int tt = lane + G * i;
-        if (tt < N) W.yl[tt] = s;
-      }
-      W.sync();
-      int fresh = 0, lu_ok = 1;
-      if (force_lu || !lu_valid || fabs(c / c_lu - 1.0) > kLuGammaDrift || lu_age >= kLuMaxAge) {
-        lu_ok = W.newton_matrix_lu(c);
-        cs.n_jac++;
-        cs.n_lu++;
-        lu_valid = lu_ok;
-        c_lu = c;
-        lu_age = 0;
-        crate = 1.0;
-        fresh = 1;
-      }
-      bool conv = false;
-      int nonfin = 0;
-      if (lu_ok) {
-        double dn_old = 0.0;
-        for (int it = 0; it < sp.newton_maxit; ++it) {
-          if (it > 0) {
-#pragma unroll
-            for (int i = 0; i < NPL; ++i) {
-              const int tt = lane + G * i;
-              if (tt < N) W.yl[tt] = yv[i];
-            }
-            W.sync();
-          }
-          if (full && (it > 0 || !fresh)) {
-            lu_ok = W.newton_matrix_lu(c);   // Jacobian at the current iterate
-            cs.n_jac++;
-            cs.n_lu++;
-            lu_valid = lu_ok;
-            c_lu = c;
-            lu_age = 0;
-            crate = 1.0;
-            fresh = 1;
-            if (!lu_ok) break;
-          }
-          const double scale = (c == c_lu) ? 1.0 : 2.0 / (1.0 + c / c_lu);
-          double f[NPL];
-          W.forcing(f);
-          cs.n_f++;
-          int nf = 0;
-#pragma unroll
-          for (int i = 0; i < NPL; ++i) {
-            const int tt = lane + G * i;
-            if (tt < N) {
-              if (!isfinite(f[i])) nf = 1;
-              W.xl[tt] = c * f[i] - psi[i] - d[i];
-            }
-          }
-          if (W.any(nf)) { nonfin = 1; break; }
-          W.sync();
-          W.solve();
-          double dl[NPL];
-#pragma unroll
-          for (int i = 0; i < NPL; ++i) {
-            const int tt = lane + G * i;
-            dl[i] = tt < N ? W.xl[tt] * scale : 0.0;
-          }
-          W.sync();
-          const double dn = W.wrms(dl, w);
-          cs.newton_iters++;
-#pragma unroll
-          for (int i = 0; i < NPL; ++i) {
-            yv[i] += dl[i];
-            d[i] += dl[i];
-          }
-          if (!isfinite(dn)) break;
-          if (it > 0) crate = fmax(0.3 * crate, dn / dn_old);
-          const double dcon = dn * fmin(1.0, crate) / sp.newton_tol;
-          if (dcon <= 1.0) { conv = true; break; }
-          if (it > 0 && dn > kNewtonDiverge * dn_old) break;
-          dn_old = dn;
-        }
-      }
-      if (nonfin) { status = ST_NONFINITE; break; }
-      if (!conv) {
-        if (!fresh && lu_ok) { force_lu = 1; continue; }
-        cs.newton_fail++;
-        if (++consec_nf >= kMaxConsecFail) { status = ST_NEWTON_FAIL; break; }
-        rescale_hist(D, q, 0.25);
-        h *= 0.25;
-        n_equal = 0;
-        force_lu = 0;
-        continue;
-      }
-      force_lu = 0;
-      // positivity constraint: a converged solution more than one tolerance unit below
-      // zero is rejected and retried with a smaller step (values are never clipped)
-      int neg = 0;
-#pragma unroll
-      for (int i = 0; i < NPL; ++i)
-        if (lane + G * i < N && yv[i] * w[i] < -1.0) neg = 1;
-      if (W.any(neg)) {
-        cs.rejected++;
-        rescale_hist(D, q, kConstraintFactor);
-        h *= kConstraintFactor;
-        n_equal = 0;
-        continue;
-      }
-      double dq1[NPL];
-#pragma unroll
-      for (int i = 0; i < NPL; ++i) dq1[i] = d[i] / (q + 1);
-      err = W.wrms(dq1, w);
-      if (err > 1.0) {
-        cs.rejected++;
-        if (++consec_err >= kMaxConsecFail) { status = ST_ERR_FAIL; break; }
-        n_equal = 0;
-        if (consec_err >= kErrRestart) {
-          // restart at order 1 from y_n with a much smaller step: D[1] = h f(y_n)
-#pragma unroll
-          for (int i = 0; i < NPL; ++i) {
-            const int tt = lane + G * i;
-            if (tt < N) W.yl[tt] = D[0][i];
-          }
-          W.sync();
-          double fn[NPL];
-          W.forcing(fn);
-          cs.n_f++;
-          h *= kRestartFactor;
-          q = 1;
-#pragma unroll
-          for (int i = 0; i < NPL; ++i) {
-            D[1][i] = h * fn[i];
-#pragma unroll
-            for (int j = 2; j < kHist; ++j) D[j][i] = 0.0;
-          }
-          continue;
-        }
-        double rho = fmax(kMinFactor, kSafety * pow(err, -1.0 / (q + 1)));
-        if (consec_err >= 2) rho = fmin(rho, kMinFactor);
-        rescale_hist(D, q, rho);
-        h *= rho;
-        continue;
-      }
-      accepted = true;
-      break;
-    }
-    if (!accepted) break;
-
-    // ---- accept: advance time and update the differences ----
-    cs.steps++;
-    lu_age++;
-    t = (span - (t + h) <= 1e-12 * span) ? span : t + h;
-    n_equal++;
-#pragma unroll
-    for (int i = 0; i < NPL; ++i) {
-      double old_q1 = 0.0;
-#pragma unroll
-      for (int j = 1; j < kHist; ++j)
-        if (j == q + 1) old_q1 = D[j][i];
-      double s = d[i];
-#pragma unroll
-      for (int j = kMaxOrder; j >= 0; --j)
-        if (j <= q) {
-          s += D[j][i];
-          D[j][i] = s;
-        }
-#pragma unroll
-      for (int j = 1; j < kHist; ++j) {
-        if (j == q + 1) D[j][i] = d[i];
-        if (j == q + 2) D[j][i] = d[i] - old_q1;
-      }
-    }
-    if (t >= span) break;
-    if (n_equal < q + 1) continue;
-    double vm[NPL], vp[NPL];
-#pragma unroll
-    for (int i = 0; i < NPL; ++i) {
-      vm[i] = 0.0;
-      vp[i] = 0.0;
-#pragma unroll
-      for (int j = 1; j < kHist; ++j) {
-        if (j == q) vm[i] = D[j][i];
-        if (j == q + 2) vp[i] = D[j][i];
-      }
-    }
-    const double err_m = q > 1 ? W.wrms(vm, w) / q : 0.0;
-    const double err_p = q < sp.max_order ? W.wrms(vp, w) / (q + 2) : 0.0;
-    double rho;
-    q = choose_order(q, sp.max_order, err, err_m, err_p, &rho);
-    rescale_hist(D, q, rho);
-    h *= rho;
-    n_equal = 0;
-  }
-
-  if (status == ST_OK) {
-#pragma unroll
-    for (int i = 0; i < NPL; ++i) {
-      const int tt = lane + G * i;
-      if (tt < N) yrow[m.perm[tt]] = D[0][i];
-    }
-  }
-  cs.order = q;
-  return status;
-}
-
-// Rate constants, then the integration; a cell whose integration fails (too many steps,
-// step below the minimum, repeated error-test or Newton failures) is integrated again from
-// its input: with full Newton, then with full Newton and a tighter absolute tolerance.
-template <int NPL, int G>
-__device__ void solve_one_cell(const DevMech& m, const DevEnv& env, double* state, int cell,
-                               const SolveParams& sp, int* status_out, camp_cell_stats* stats_out,
-                               const WaveCell<NPL, G>& W) {
-  const int lane = W.lane;
-  camp_cell_stats cs = {0, 0, 0, 0, 0, 0, 0, 0};
-  const double Tk = env.T[cell], Pp = env.P[cell];
-  const double cz = env.cos_sza ? env.cos_sza[cell] : 1.0;
-  const double* rad = env.radius ? env.radius + (size_t)cell * m.n_inst : nullptr;
-  const double* mas = env.mass ? env.mass + (size_t)cell * m.n_inst : nullptr;
-  const double* ovr = env.override_ ? env.override_ + (size_t)cell * m.n_ext : nullptr;
-  int bad = 0;
-  for (int k = lane; k < m.R; k += G) {
-    const double v = rate_constant(m, k, Tk, Pp, cz, rad, mas, ovr);
-    W.kc[k] = v;
-    if (!isfinite(v)) bad = 1;
-  }
-  __threadfence_block();   // rate constants (LDS or global scratch) visible to all lanes
-  double* yrow = state + (size_t)cell * m.N;
-  int status = ST_OK;
-  for (int attempt = sp.full_newton ? 1 : 0; attempt < kAttempts; ++attempt) {
-    SolveParams spa = sp;
-    if (attempt == 2) spa.atol *= kRetryAtolFactor;
-    status = integrate<NPL, G>(m, yrow, spa, bad, attempt > 0, cs, W);
-    if (status < ST_MAX_STEPS || status > ST_NEWTON_FAIL) break;
-  }
-  if (lane == 0) {
-    status_out[cell] = status;
-    if (stats_out) stats_out[cell] = cs;
-  }
-  W.sync();
-}
-
-// Launch modes of the wavefront engine (table staging and where rate constants live):
-//   0  tables read from global memory, rate constants in LDS
-//   1  core index tables staged in LDS
-//   2  whole table block staged in LDS
-//   3  tables from global memory and rate constants in a global per-wavefront scratch
-//      (persistent launches only), for mechanisms whose per-cell LDS is the occupancy limit
-//   4  core index tables staged in LDS and rate constants in the global scratch
-// In modes 3 and 4 a mechanism of at most 128 state variables runs a kernel built for
-// three wavefronts per SIMD (at most 168 registers), with up to 12 cells per workgroup.
-__host__ __device__ constexpr bool kc_global(int mode) { return mode >= 3; }
-
-// LDS doubles of one cell: M [Z], y [N], x [N], partials/rates, 8 doubles of group
-// scratch, and the rate constants unless they live in global scratch (modes 3, 4).
-__host__ __device__ inline size_t cell_doubles(const DevMech& m, int mode) {
-  const int np = m.n_part > m.R ? m.n_part : m.R;
-  return (size_t)m.Z + 2 * (size_t)m.N + np + 8 + (kc_global(mode) ? 0 : m.R);
-}
-
-// Bytes of the table block staged in LDS in launch mode `mode`.
-__host__ __device__ inline int staged_bytes(const StageView& v, int mode) {
-  return mode == 2 ? v.bytes : (mode == 1 || mode == 4) ? v.core_bytes : 0;
-}
-
-// Copies the staged part of the table block into LDS (16-byte units).
-template <int kStage>
-__device__ __forceinline__ Tabs stage_tables(const StageView& v, double* lds) {
-  const char* g = reinterpret_cast<const char*>(v.base);
-  if (kStage == 0 || kStage == 3) return Tabs{g, g, v};
-  const uint4* src = reinterpret_cast<const uint4*>(v.base);
-  uint4* dst = reinterpret_cast<uint4*>(lds);
-  const int n16 = staged_bytes(v, kStage) / 16;
-  for (int i = threadIdx.x; i < n16; i += blockDim.x) dst[i] = src[i];
-  __syncthreads();
-  const char* l = reinterpret_cast<const char*>(lds);
-  return Tabs{l, kStage == 2 ? l : g, v};
-}
-
-}  // namespace
-
-// One wavefront per cell (G = 64): up to 3 species per lane the kernel fits 256 VGPRs (two
-// wavefronts per SIMD, workgroups of up to 8 cells); larger states get 512 VGPRs
-// (workgroups of up to 4 cells). In modes 3 and 4, up to 2 species per lane the kernel is
-// built for 168 registers (three wavefronts per SIMD, workgroups of up to 12 cells).
-// One workgroup per cell (G = 128 or 256): at most 256 VGPRs (two wavefronts per SIMD).
-template <int NPL, int kMode, int G>
-constexpr bool occ3() { return G == kWave && NPL <= 2 && kc_global(kMode); }
-template <int NPL, int kMode, int G>
-constexpr int max_threads() {
-  return G > kWave ? G : kWave * (occ3<NPL, kMode, G>() ? 12 : NPL <= 3 ? 8 : 4);
-}
-template <int NPL, int kMode, int G>
-constexpr int min_waves_per_simd() { return G > kWave ? 2 : occ3<NPL, kMode, G>() ? 3 : 1; }
 
 int wave_lanes_ok(int n_state, int lanes) {
   if (lanes == 64) return (n_state + 63) / 64 <= 9;
@@ -822,52 +20,8 @@ int wave_max_waves(int n_state, int mode, int lanes) {
 
 int wave_resident_cells_per_cu(int n_state, int mode, int lanes) {
   if (lanes == 64) return wave_max_waves(n_state, mode, 64);
-  return 8 / (lanes / 64);   // two wavefronts per SIMD, four SIMDs
-}
-
-// G = 64: blockDim.x = 64 * W, W wavefronts, one cell each; G > 64: blockDim.x = G, one
-// cell per workgroup. queue != nullptr: persistent grid pulling cells from the counter;
-// else cell = blockIdx.x * W + wavefront. Modes 3 and 4 keep the rate constants at
-// kc_glob + (blockIdx.x * W + wavefront) * R and need the queue.
-template <int NPL, int kStage, int G>
-__global__ __launch_bounds__((max_threads<NPL, kStage, G>()),
-                             (min_waves_per_simd<NPL, kStage, G>())) void bdf_wave_kernel(
-    DevMech m, DevEnv env, double* state, int n_cells, SolveParams sp, int* status,
-    camp_cell_stats* stats, int* queue, double* kc_glob) {
-  extern __shared__ double lds[];
-  const StageView& view = m.sv[G / 128];
-  const Tabs tab = stage_tables<kStage>(view, lds);
-  const int W = G == kWave ? blockDim.x / kWave : 1;
-  const int wid = G == kWave ? threadIdx.x / kWave : 0;
-  const int lane = threadIdx.x % G;
-  double* base = lds + staged_bytes(view, kStage) / 8 + wid * cell_doubles(m, kStage);
-  const int np = m.n_part > m.R ? m.n_part : m.R;
-  double* yl = base + m.Z;
-  double* xl = yl + m.N;
-  double* P = xl + m.N;
-  double* red = P + np;
-  double* kc = kc_global(kStage) ? kc_glob + (size_t)(blockIdx.x * W + wid) * m.R : red + 8;
-  const WaveCell<NPL, G> Wc{m, tab, base, yl, xl, P, kc, red, lane};
-  if (!queue) {
-    const int cell = blockIdx.x * W + wid;
-    if (cell < n_cells) solve_one_cell<NPL, G>(m, env, state, cell, sp, status, stats, Wc);
-    return;
-  }
-  while (true) {
-    int cell = 0;
-    if constexpr (G == kWave) {
-      if (lane == 0) cell = atomicAdd(queue, 1);
-      cell = uniform(cell);
-    } else {
-      int* slot = reinterpret_cast<int*>(red + 4);
-      if (threadIdx.x == 0) *slot = atomicAdd(queue, 1);
-      __syncthreads();
-      cell = *slot;
-      __syncthreads();
-    }
-    if (cell >= n_cells) break;
-    solve_one_cell<NPL, G>(m, env, state, cell, sp, status, stats, Wc);
-  }
+  const int per_simd = (n_state + lanes - 1) / lanes <= 3 ? 2 : 1;   // see min_waves_per_simd
+  return 4 * per_simd / (lanes / 64);
 }
 
 size_t wave_cell_bytes(const DevMech& m) { return sizeof(double) * cell_doubles(m, 0); }
@@ -881,46 +35,6 @@ size_t wave_wg_lds_bytes(const DevMech& m, int waves, int mode, int lanes) {
          (size_t)waves * sizeof(double) * cell_doubles(m, mode);
 }
 
-template <int NPL, int kStage, int G>
-hipError_t launch_wave_npl(const DevMech& m, const DevEnv& env, double* state, int n_cells,
-                           const SolveParams& sp, int* status, camp_cell_stats* stats, int* queue,
-                           double* kc_glob, int grid, int waves, size_t lds, hipStream_t stream) {
-  hipError_t e = hipFuncSetAttribute((const void*)bdf_wave_kernel<NPL, kStage, G>,
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  if (e != hipSuccess) return e;
-  const int threads = G == kWave ? kWave * waves : G;
-  hipLaunchKernelGGL((bdf_wave_kernel<NPL, kStage, G>), dim3(grid), dim3(threads), lds, stream,
-                     m, env, state, n_cells, sp, status, stats, queue, kc_glob);
-  return hipGetLastError();
-}
-
-struct WaveLaunch {
-  const DevMech& m;
-  const DevEnv& env;
-  double* state;
-  int n_cells;
-  const SolveParams& sp;
-  int* status;
-  camp_cell_stats* stats;
-  int* queue;
-  double* kc_glob;
-  int grid, waves;
-  size_t lds;
-  hipStream_t stream;
-
-  template <int NPL, int G>
-  hipError_t run(int stage) const {
-    switch (stage) {
-      case 0: return launch_wave_npl<NPL, 0, G>(m, env, state, n_cells, sp, status, stats, queue, kc_glob, grid, waves, lds, stream);
-      case 1: return launch_wave_npl<NPL, 1, G>(m, env, state, n_cells, sp, status, stats, queue, kc_glob, grid, waves, lds, stream);
-      case 2: return launch_wave_npl<NPL, 2, G>(m, env, state, n_cells, sp, status, stats, queue, kc_glob, grid, waves, lds, stream);
-      case 3: return launch_wave_npl<NPL, 3, G>(m, env, state, n_cells, sp, status, stats, queue, kc_glob, grid, waves, lds, stream);
-      case 4: return launch_wave_npl<NPL, 4, G>(m, env, state, n_cells, sp, status, stats, queue, kc_glob, grid, waves, lds, stream);
-      default: return hipErrorInvalidValue;
-    }
-  }
-};
-
 hipError_t launch_bdf_wave(const DevMech& m, const DevEnv& env, double* state, int n_cells,
                            const SolveParams& sp, int* status, camp_cell_stats* stats, int* queue,
                            double* kc_glob, int grid, int waves, int stage, int lanes,
@@ -931,40 +45,17 @@ hipError_t launch_bdf_wave(const DevMech& m, const DevEnv& env, double* state, i
   if (!view.base || view.wave_lists != lanes / kWave) return hipErrorInvalidValue;
   if (waves < 1 || waves > wave_max_waves(m.N, stage, lanes)) return hipErrorInvalidValue;
   if (kc_global(stage) && (!queue || !kc_glob)) return hipErrorInvalidValue;
-  const WaveLaunch L{m, env, state, n_cells, sp, status, stats, queue, kc_glob, grid, waves,
+  const WaveParams p{m, env, state, n_cells, sp, status, stats, queue, kc_glob, grid, waves,
                      wave_wg_lds_bytes(m, waves, stage, lanes), stream};
   const int npl = (m.N + lanes - 1) / lanes;
-  if (lanes == 64) {
-    switch (npl) {
-      case 1: return L.run<1, 64>(stage);
-      case 2: return L.run<2, 64>(stage);
-      case 3: return L.run<3, 64>(stage);
-      case 4: return L.run<4, 64>(stage);
-      case 5: return L.run<5, 64>(stage);
-      case 6: return L.run<6, 64>(stage);
-      case 7: return L.run<7, 64>(stage);
-      case 8: return L.run<8, 64>(stage);
-      case 9: return L.run<9, 64>(stage);
-      default: return hipErrorInvalidValue;
-    }
-  }
-  if (lanes == 128) {
-    switch (npl) {
-      case 1: return L.run<1, 128>(stage);
-      case 2: return L.run<2, 128>(stage);
-      case 3: return L.run<3, 128>(stage);
-      case 4: return L.run<4, 128>(stage);
-      case 5: return L.run<5, 128>(stage);
-      default: return hipErrorInvalidValue;
-    }
-  }
-  switch (npl) {
-    case 1: return L.run<1, 256>(stage);
-    case 2: return L.run<2, 256>(stage);
-    case 3: return L.run<3, 256>(stage);
-    default: return hipErrorInvalidValue;
-  }
+  if (lanes == 128) return wave_run_128(p, npl, stage);
+  if (lanes == 256) return wave_run_256(p, npl, stage);
+  if (npl <= 3) return wave_run_64_a(p, npl, stage);
+  if (npl <= 6) return wave_run_64_b(p, npl, stage);
+  return wave_run_64_c(p, npl, stage);
 }
+
+namespace {
 
 // ---------------------------------------------------------------- single-step kernels
 // One wavefront per cell; the same device code as the fused engine (tables read from
@@ -1027,6 +118,8 @@ __global__ void rates_step_kernel(DevMech m, DevEnv env, int n_cells, double* k_
   k_out[idx] = rate_constant(m, r, env.T[cell], env.P[cell], env.cos_sza ? env.cos_sza[cell] : 1.0,
                              rad, mas, ovr);
 }
+
+}  // namespace
 
 hipError_t launch_rates_step(const DevMech& m, const DevEnv& env, int n_cells, double* k_out,
                              hipStream_t stream) {
