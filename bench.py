@@ -28,14 +28,15 @@ HBM_PEAK_GBS = 8000.0
 # HBM traffic of the dominant kernel per launch, from rocprofv3 --pmc FETCH_SIZE and
 # WRITE_SIZE runs of this script (KiB per dispatch), each scaled by the ratio of the known
 # size to the counter's reading for a plain device copy (`--calibrate-copy`). Valid only
-# for the kernel sources it was taken with (their SHA-256 prefix); otherwise reported null.
+# for the kernel and table-compiler sources it was taken with (their SHA-256 prefix);
+# otherwise reported null.
 KERNEL_SOURCES = ["paper_2111_07436_amd/csrc/engine_wave.hpp", "paper_2111_07436_amd/csrc/device.hpp",
-                  "paper_2111_07436_amd/csrc/bdf_common.hpp"]
+                  "paper_2111_07436_amd/csrc/bdf_common.hpp", "paper_2111_07436_amd/csrc/compile.cpp"]
 MEASURED_TRAFFIC = {
     # bdf_wave_kernel<2, 4, 64> (launch mode 4, 12 cells per workgroup, 256 workgroups,
     # persistent; the autotuner's pick), mean of the timed launches
-    "c2": {"fetch_kib": 84946.1, "fetch_scale": 1048576 / 524300.0,
-           "write_kib": 74558.9, "write_scale": 1048576 / 1048576.0, "sources": "88b024731c1fe625"},
+    "c2": {"fetch_kib": 86050.2, "fetch_scale": 1048576 / 524300.0,
+           "write_kib": 74892.4, "write_scale": 1048576 / 1048576.0, "sources": "fa70b6fdd028aa9e"},
 }
 
 WORKLOADS = {
