@@ -188,10 +188,14 @@ typedef struct {
                         /* workgroup per cell batch, -1 = auto                        */
   int use_graph;        /* PLAIN: 1 = replay a captured hipGraph of each chunk of     */
                         /* step-attempt launches                                      */
-  int waves_per_wg;     /* FUSED_WAVE: wavefronts (cells) per workgroup 1..8, 0 = auto */
-  int stage_tables;     /* FUSED_WAVE tables in LDS: 0 = none (global), 1 = sparse-index */
-                        /* tables, 2 = all (also forcing terms and Jacobian map),      */
-                        /* -1 = auto                                                   */
+  int waves_per_wg;     /* FUSED_WAVE, one wavefront per cell: cells per workgroup      */
+                        /* 1..8 (1..12 in launch modes 3, 4 up to 128 state variables),*/
+                        /* 0 = auto                                                    */
+  int stage_tables;     /* FUSED_WAVE launch mode: 0 = tables read from global memory, */
+                        /* 1 = sparse-index tables staged in LDS, 2 = all tables in    */
+                        /* LDS (also forcing terms and Jacobian map), 3 / 4 = as 0 / 1 */
+                        /* with the rate constants in a global per-cell-slot scratch   */
+                        /* (persistent grid), -1 = auto                                */
   int lanes_per_cell;   /* FUSED_WAVE: 64 = one wavefront per cell, 128 or 256 = one     */
                         /* workgroup of 2 or 4 wavefronts per cell (more than 64 / 128  */
                         /* state variables), 0 = auto                                   */
