@@ -202,6 +202,18 @@ typedef struct {
   int full_newton;      /* 0 (default): Newton with Jacobian reuse; a cell that fails   */
                         /* (status 1-4) is integrated again from its input with full    */
                         /* Newton. 1: full Newton (fresh Jacobian and LU every iteration)*/
+  const int* cell_order;/* NULL (default), or a permutation of 0..n_cells-1 giving the   */
+                        /* order in which a persistent wavefront-engine launch takes     */
+                        /* cells from its queue (for example costliest first, by the     */
+                        /* per-cell counters of the previous host step, so the last      */
+                        /* cells to start are short). Device memory for                  */
+                        /* camp_solve_device and the server (it must stay valid until    */
+                        /* the solve has run on the stream), host memory for camp_solve. */
+                        /* camp_solve rejects a non-permutation with CAMP_EINVAL; on the */
+                        /* device path it is checked on the stream and, if it is not a   */
+                        /* permutation, ignored (cells run in index order). Other        */
+                        /* engines and non-persistent launches ignore it. Results never  */
+                        /* depend on the order: each cell is integrated alone.           */
 } camp_opts;
 
 /* Per-cell counters (optional output). */

@@ -74,7 +74,7 @@ class Opts(C.Structure):
                 ("h_min", C.c_double), ("h_init", C.c_double), ("engine", C.c_int),
                 ("wg_per_cu", C.c_int), ("persistent", C.c_int), ("use_graph", C.c_int),
                 ("waves_per_wg", C.c_int), ("stage_tables", C.c_int), ("lanes_per_cell", C.c_int),
-                ("full_newton", C.c_int)]
+                ("full_newton", C.c_int), ("cell_order", C.c_void_p)]
 
 
 class CellStats(C.Structure):
@@ -136,10 +136,25 @@ def _stream():
 
 def make_opts(engine="auto", max_order=0, max_steps=0, newton_max_iter=0, h_min=0.0, h_init=0.0,
               wg_per_cu=0, persistent=-1, use_graph=0, waves_per_wg=0, stage_tables=-1,
-              lanes_per_cell=0, full_newton=0):
+              lanes_per_cell=0, full_newton=0, cell_order=None):
+    """camp_opts; ``cell_order`` is an int32 torch tensor (device solves) or numpy array
+    (host solves) holding a permutation of the cells, kept alive by the returned object."""
     e = ENGINES[engine] if isinstance(engine, str) else int(engine)
-    return Opts(max_order, max_steps, newton_max_iter, h_min, h_init, e, wg_per_cu,
-                persistent, use_graph, waves_per_wg, stage_tables, lanes_per_cell, full_newton)
+    ptr = None
+    if cell_order is not None:
+        if isinstance(cell_order, np.ndarray):
+            if cell_order.dtype != np.int32 or not cell_order.flags.c_contiguous:
+                raise ValueError("cell_order must be a contiguous int32 array")
+            ptr = cell_order.ctypes.data
+        else:
+            import torch
+            if cell_order.dtype != torch.int32 or not cell_order.is_contiguous():
+                raise ValueError("cell_order must be a contiguous int32 tensor")
+            ptr = cell_order.data_ptr()
+    o = Opts(max_order, max_steps, newton_max_iter, h_min, h_init, e, wg_per_cu,
+             persistent, use_graph, waves_per_wg, stage_tables, lanes_per_cell, full_newton, ptr)
+    o._keep = cell_order
+    return o
 
 
 class Mech:

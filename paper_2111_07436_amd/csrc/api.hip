@@ -213,6 +213,8 @@ SolveParams make_params(double dt, double rtol, double atol, const camp_opts* o)
   sp.h_init = (o && o->h_init > 0) ? o->h_init : 0.0;
   sp.newton_tol = 0.1;
   sp.full_newton = (o && o->full_newton) ? 1 : 0;
+  sp.order = nullptr;
+  sp.order_bad = nullptr;
   return sp;
 }
 
@@ -270,17 +272,28 @@ int solve_device_tuned(camp_mech* mh, const DevMech& dm, int n_cells, double* d_
     }
     const int wg_total = (n_cells + waves - 1) / waves;
     if (tu.persistent || stage >= 3) {
-      // queue counter, then (mode 3) the rate-constant scratch of every resident wavefront
+      // 256 bytes: queue counter (int 0) and cell-order flag (int 16); then (modes 3, 4) the
+      // rate-constant scratch of every resident wavefront; then, with a cell order, one
+      // counter per cell for its permutation check
       const int grid = std::max(1, std::min(wg_total, n_cus() * std::max(1, tu.grid_mult)));
       const size_t kc_bytes = stage >= 3 ? sizeof(double) * (size_t)grid * waves * dm.R : 0;
+      const int* order = opts ? opts->cell_order : nullptr;
+      const size_t seen_bytes = order ? sizeof(int) * (size_t)n_cells : 0;
       char* buf = nullptr;
-      e = hipMallocAsync((void**)&buf, 256 + kc_bytes, stream);
+      e = hipMallocAsync((void**)&buf, 256 + kc_bytes + seen_bytes, stream);
       if (e != hipSuccess) return hip_fail(e, "hipMallocAsync(queue)");
       int* queue = reinterpret_cast<int*>(buf);
       double* kc = stage >= 3 ? reinterpret_cast<double*>(buf + 256) : nullptr;
-      e = launch_fill_int(queue, 1, 0, stream);
+      SolveParams spo = sp;
+      e = launch_fill_int(queue, 64, 0, stream);
+      if (e == hipSuccess && order) {
+        spo.order = order;
+        spo.order_bad = queue + 16;
+        e = launch_check_order(order, n_cells, reinterpret_cast<int*>(buf + 256 + kc_bytes),
+                               queue + 16, stream);
+      }
       if (e == hipSuccess)
-        e = launch_bdf_wave(dm, env, d_state, n_cells, sp, d_status, d_stats, queue, kc, grid,
+        e = launch_bdf_wave(dm, env, d_state, n_cells, spo, d_status, d_stats, queue, kc, grid,
                             waves, stage, tu.lanes, stream);
       hipError_t e2 = hipFreeAsync(buf, stream);
       if (e == hipSuccess) e = e2;
@@ -435,6 +448,13 @@ int camp_solve_device(camp_mech* mh, int n_cells, double* d_state, const camp_en
     if (opts->waves_per_wg > 0) tu.waves = std::min(opts->waves_per_wg, 12);
     if (opts->lanes_per_cell > 0) tu.lanes = opts->lanes_per_cell;
     if (opts->stage_tables >= 0) tu.stage = std::min(opts->stage_tables, 4);
+    if (opts->waves_per_wg <= 0 && tu.engine == CAMP_ENGINE_FUSED_WAVE && tu.lanes == 64 &&
+        tu.stage >= 0) {
+      // cells per workgroup not given: the most that this launch mode allows and LDS holds
+      int w = std::min(tu.waves, wave_max_waves(dm->N, tu.stage, 64));
+      while (w > 1 && wave_wg_lds_bytes(*dm, w, tu.stage, 64) > kLdsBytes) --w;
+      tu.waves = std::max(1, w);
+    }
   }
   return solve_device_tuned(mh, *dm, n_cells, d_state, d_env, sp, opts, d_status, d_stats,
                             (hipStream_t)stream, tu);
@@ -467,10 +487,24 @@ int camp_solve(camp_mech* mh, int n_cells, double* state, const camp_env* env, d
   add(4, C.n_inst ? env->radius_m : nullptr, bytes_inst);
   add(5, C.n_inst ? env->aer_mass_kg_m3 : nullptr, bytes_inst);
   add(6, env->rate_override, bytes_ovr);
+  const int* order = opts ? opts->cell_order : nullptr;
+  if (order) {
+    std::vector<char> seen(n, 0);
+    for (size_t i = 0; i < n; ++i) {
+      const int c = order[i];
+      if (c < 0 || (size_t)c >= n || seen[c]) {
+        set_error("opts->cell_order must be a permutation of 0..n_cells-1");
+        return CAMP_EINVAL;
+      }
+      seen[c] = 1;
+    }
+  }
   const size_t off_status = total;
   total = align256(total + 4 * n);
   const size_t off_stats = total;
   if (cell_stats) total = align256(total + sizeof(camp_cell_stats) * n);
+  const size_t off_order = total;
+  if (order) total = align256(total + 4 * n);
   char* d = nullptr;
   hipError_t e = hipMalloc((void**)&d, total);
   if (e != hipSuccess) return hip_fail(e, "hipMalloc(solve buffers)");
@@ -486,8 +520,15 @@ int camp_solve(camp_mech* mh, int n_cells, double* state, const camp_env* env, d
                 parts[6].bytes ? (const double*)(d + parts[6].off) : nullptr};
   int* d_status = (int*)(d + off_status);
   camp_cell_stats* d_stats = cell_stats ? (camp_cell_stats*)(d + off_stats) : nullptr;
-  rc = camp_solve_device(mh, n_cells, (double*)(d + parts[0].off), &denv, dt, rtol, atol, opts,
-                         d_status, d_stats, nullptr);
+  camp_opts dopts{};
+  if (opts) dopts = *opts;
+  if (order) {
+    e = hipMemcpy(d + off_order, order, 4 * n, hipMemcpyHostToDevice);
+    if (e != hipSuccess) { hipFree(d); return hip_fail(e, "hipMemcpy H2D"); }
+    dopts.cell_order = (const int*)(d + off_order);
+  }
+  rc = camp_solve_device(mh, n_cells, (double*)(d + parts[0].off), &denv, dt, rtol, atol,
+                         opts ? &dopts : nullptr, d_status, d_stats, nullptr);
   if (rc == CAMP_OK) {
     e = hipDeviceSynchronize();
     if (e != hipSuccess) rc = hip_fail(e, "solve");

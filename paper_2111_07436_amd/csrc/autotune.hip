@@ -192,6 +192,10 @@ int autotuned(camp_mech* mh, const DevMech& dm, int n_cells, double* d_state,
   if (e == hipSuccess) e = hipEventCreate(&b);
   best = default_tuning(dm, n_cells);
   best.ms = 1e30;
+  // trials take cells in index order (a caller's cell order spans the whole call)
+  camp_opts topts{};
+  if (opts) topts = *opts;
+  topts.cell_order = nullptr;
   if (e == hipSuccess) {
     for (Tuning t : candidates(dm)) {
       // up to two timed runs on identical copies (min); a candidate far slower than the
@@ -204,7 +208,7 @@ int autotuned(camp_mech* mh, const DevMech& dm, int n_cells, double* d_state,
           break;
         }
         hipEventRecord(a, stream);
-        rc = solve_device_tuned(mh, dm, trial, work, d_env, sp, opts, st, nullptr, stream, t);
+        rc = solve_device_tuned(mh, dm, trial, work, d_env, sp, &topts, st, nullptr, stream, t);
         hipEventRecord(b, stream);
         if (hipEventSynchronize(b) != hipSuccess) rc = CAMP_EDEVICE;
         float ms = 0.f;

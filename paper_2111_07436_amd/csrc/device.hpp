@@ -78,6 +78,10 @@ struct SolveParams {
   double dt, rtol, atol, h_min, h_init, newton_tol;
   int max_order, max_steps, newton_maxit;
   int full_newton;   // 1: full Newton from the start (no Jacobian reuse)
+  // Persistent wavefront launches: queue position -> cell, used unless *order_bad != 0
+  // (both null: index order).
+  const int* order;
+  const int* order_bad;
 };
 
 // BDF coefficients: gamma_q = sum_{j=1}^{q} 1/j; local error constant 1/(q+1).

@@ -2,6 +2,7 @@
 // to the kernel instantiation for its species per lane, group size and launch mode; and the
 // single-step kernels behind the step entry points.
 #include "engine_wave.hpp"
+#include "runtime.hpp"
 
 namespace camp {
 
@@ -108,6 +109,15 @@ __global__ __launch_bounds__(kWave) void wave_step_kernel(DevMech m, int op, int
   }
 }
 
+// seen[0..n) starts at zero; *bad becomes nonzero unless order is a permutation of 0..n-1
+// (n entries, each in range and none repeated).
+__global__ void check_order_kernel(const int* order, int n, int* seen, int* bad) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int c = order[i];
+  if (c < 0 || c >= n || atomicAdd(seen + c, 1) != 0) atomicOr(bad, 1);
+}
+
 __global__ void rates_step_kernel(DevMech m, DevEnv env, int n_cells, double* k_out) {
   const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= (long long)n_cells * m.R) return;
@@ -120,6 +130,14 @@ __global__ void rates_step_kernel(DevMech m, DevEnv env, int n_cells, double* k_
 }
 
 }  // namespace
+
+hipError_t launch_check_order(const int* order, int n, int* seen, int* bad, hipStream_t stream) {
+  hipError_t e = launch_fill_int(seen, n, 0, stream);
+  if (e != hipSuccess || n <= 0) return e;
+  hipLaunchKernelGGL(check_order_kernel, dim3((n + 255) / 256), dim3(256), 0, stream, order, n,
+                     seen, bad);
+  return hipGetLastError();
+}
 
 hipError_t launch_rates_step(const DevMech& m, const DevEnv& env, int n_cells, double* k_out,
                              hipStream_t stream) {

@@ -870,6 +870,7 @@ __global__ __launch_bounds__((max_threads<NPL, kStage, G>()),
       __syncthreads();
     }
     if (cell >= n_cells) break;
+    if (sp.order && *sp.order_bad == 0) cell = sp.order[cell];
     solve_one_cell<NPL, G>(m, env, state, cell, sp, status, stats, Wc);
   }
 }

@@ -63,6 +63,8 @@ hipError_t run_fused_lane(const DevMech& m, const DevEnv& env, double* state, in
                           int n_slots, hipStream_t stream);
 hipError_t launch_count_failed(int n, const int* status, int* out, hipStream_t stream);
 hipError_t launch_fill_int(int* p, int n, int v, hipStream_t stream);
+// Zeroes seen[0..n) and raises *bad (not cleared here) unless order[0..n) is a permutation.
+hipError_t launch_check_order(const int* order, int n, int* seen, int* bad, hipStream_t stream);
 
 }  // namespace camp
 

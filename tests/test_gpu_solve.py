@@ -221,6 +221,33 @@ def test_workgroup_per_cell_parity(torch, lanes):
     assert np.array_equal(y, ref)
 
 
+def test_cell_order_identical(torch):
+    """A caller's cell order changes which slot integrates a cell and when, not the
+    arithmetic: states are bit-identical to index order for every group size; an order
+    that is not a permutation is ignored on the device path; the host-array entry point
+    takes a host order and gives the same states."""
+    from paper_2111_07436_amd import camp
+    for name, n, lanes, mode in (("c2", 500, 64, 3), ("c2", 500, 64, 0), ("c3", 70, 128, 3),
+                                 ("c3", 70, 256, 1)):
+        wl = W.make_workload(name, n_cells=n)
+        m = camp.Mech(wl.mech)
+        kw = dict(lanes_per_cell=lanes, stage_tables=mode, persistent=1, wg_per_cu=1)
+        log(f"{name} lanes {lanes} mode {mode}: index order")
+        ref = gpu_solve(m, wl, "wave", **kw)
+        perm = np.random.default_rng(3).permutation(n).astype(np.int32)
+        log(f"{name} lanes {lanes} mode {mode}: permuted order")
+        d_perm = torch.from_numpy(perm).cuda()
+        assert np.array_equal(gpu_solve(m, wl, "wave", cell_order=d_perm, **kw), ref)
+        dup = d_perm.clone()
+        dup[1] = dup[0]
+        log(f"{name} lanes {lanes} mode {mode}: repeated entry (ignored)")
+        assert np.array_equal(gpu_solve(m, wl, "wave", cell_order=dup, **kw), ref)
+        log(f"{name} lanes {lanes} mode {mode}: host arrays")
+        opts = camp.make_opts("wave", max_steps=20000, cell_order=perm, **kw)
+        y, st, _ = m.solve(wl.env, wl.y0, wl.dt, GPU_RTOL, GPU_ATOL, opts)
+        assert np.all(st == 0) and np.array_equal(y, ref)
+
+
 def test_plain_graph_replay_identical(torch):
     """The plain multi-kernel form replays a captured chunk of step-attempt launches; the
     states equal those of direct launches."""

@@ -100,6 +100,20 @@ def test_validation_errors():
     _expect_einval(W.Mechanism(sp[:1], [W.Phase("p", [], 1)], []))
 
 
+def test_cell_order_must_be_a_permutation():
+    """camp_solve checks a host cell order before any device work."""
+    wl = W.make_workload("c1", n_cells=8)
+    m = camp.Mech(wl.mech)
+    for bad in ([0, 1, 2, 3, 4, 5, 6, 6], [0, 1, 2, 3, 4, 5, 6, 8], [-1, 1, 2, 3, 4, 5, 6, 7]):
+        opts = camp.make_opts("wave", cell_order=np.asarray(bad, dtype=np.int32))
+        with pytest.raises(camp.CampError) as e:
+            m.solve(wl.env, wl.y0, wl.dt, 1e-4, 1e-12, opts)
+        assert e.value.code == camp.EINVAL
+        assert "cell_order" in str(e.value)
+    with pytest.raises(ValueError):
+        camp.make_opts("wave", cell_order=np.arange(8, dtype=np.int64))
+
+
 def test_schedule_counts_consistent():
     m = camp.Mech(W.make_mechanism("c2"))
     inf = m.info
