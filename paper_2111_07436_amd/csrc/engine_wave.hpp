@@ -128,6 +128,41 @@ __device__ __forceinline__ void for_terms(int lo, int hi, int lane, Gather gathe
   for (; i < hi; i += G) scatter(gather(i));
 }
 
+// A table entry of a term loop as loaded: packed indices, a second index word and a
+// coefficient (fields a loop does not use stay 0).
+struct TermEntry {
+  uint32_t e;
+  uint32_t x;
+  double c;
+};
+
+// for_terms in three phases per group, each closed by a scheduling barrier: the table
+// entries of the group are loaded (entry), then one LDS datum per entry (load), then the
+// updates are formed (make) and applied (scatter). Without the barriers the compiler,
+// short of registers, chains each entry load to its data read and each data read to its
+// use; with them a group costs one table round trip and one LDS round trip.
+template <int kU, int G, class Entry, class Load, class Make, class Scatter>
+__device__ __forceinline__ void for_terms_split(int lo, int hi, int lane, Entry entry, Load load,
+                                                Make make, Scatter scatter) {
+  int i = lo + lane;
+  for (; i + (kU - 1) * G < hi; i += kU * G) {
+    TermEntry e[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) e[u] = entry(i + u * G);
+    __builtin_amdgcn_sched_barrier(0);
+    double d[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) d[u] = load(e[u]);
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int u = 0; u < kU; ++u) scatter(make(e[u], d[u]));
+  }
+  for (; i < hi; i += G) {
+    const TermEntry e = entry(i);
+    scatter(make(e, load(e)));
+  }
+}
+
 constexpr int kTermBatch = 4;
 
 // Level pointers of a term list held in registers: lane k holds entry k and entry k + 64,
@@ -243,27 +278,61 @@ struct WaveCell {
     return sqrt(Group<G>::sum(s, red) / m.N);
   }
 
+  // Concentration factors of reaction entry t (packed reactant slots, 0x3FF = absent):
+  // the three LDS reads are issued unconditionally (an absent slot reads y[0]); yfac then
+  // turns an absent reactant's factor into 1, which leaves a product bit for bit unchanged.
+  __device__ __forceinline__ void yload(uint32_t e, double (&y)[3]) const {
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      const int a = (e >> (10 * j)) & 0x3FF;
+      y[j] = yl[a != 0x3FF ? a : 0];
+    }
+  }
+  __device__ __forceinline__ static double yfac(uint32_t e, int j, double v) {
+    return ((e >> (10 * j)) & 0x3FF) != 0x3FF ? v : 1.0;
+  }
+
+  // Reactions k = lane, lane + G, ... in groups of kTermBatch per lane: table entries of a
+  // group (entry), then its concentration reads, then use(entry, factors), with scheduling
+  // barriers between the phases as in for_terms_split.
+  template <class Entry, class Use>
+  __device__ __forceinline__ void for_reactions(Entry entry, Use use) const {
+    int k = lane;
+    for (; k + (kTermBatch - 1) * G < m.R; k += kTermBatch * G) {
+      TermEntry e[kTermBatch];
+#pragma unroll
+      for (int u = 0; u < kTermBatch; ++u) e[u] = entry(k + u * G);
+      __builtin_amdgcn_sched_barrier(0);
+      double y[kTermBatch][3];
+#pragma unroll
+      for (int u = 0; u < kTermBatch; ++u) yload(e[u].e, y[u]);
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int u = 0; u < kTermBatch; ++u) use(e[u], y[u]);
+    }
+    for (; k < m.R; k += G) {
+      const TermEntry e = entry(k);
+      double y[3];
+      yload(e.e, y);
+      use(e, y);
+    }
+  }
+
   // P[k] = r_k from yl; then f for owned species, accumulated term by term (one term per
   // lane) in xl, which no caller holds live across this call. yl must be visible to all
   // lanes.
   __device__ __forceinline__ void forcing(double (&f)[NPL]) const {
-    for (int k = lane; k < m.R; k += G) {
-      const uint32_t v = tb.rx(k);
-      const int a = v & 0x3FF, b = (v >> 10) & 0x3FF, c = (v >> 20) & 0x3FF;
-      double r = kc[k];
-      if (a != 0x3FF) r *= yl[a];
-      if (b != 0x3FF) r *= yl[b];
-      if (c != 0x3FF) r *= yl[c];
-      P[k] = r;
-    }
+    for_reactions([&](int k) { return TermEntry{tb.rx(k), (uint32_t)k, kc[k]}; },
+                  [&](const TermEntry& t, const double (&y)[3]) {
+                    P[t.x] = t.c * yfac(t.e, 0, y[0]) * yfac(t.e, 1, y[1]) * yfac(t.e, 2, y[2]);
+                  });
     for (int t = lane; t < m.N; t += G) xl[t] = 0.0;
     sync();
-    for_terms<kTermBatch, kWave>(
+    for_terms_split<kTermBatch, kWave>(
         uniform(tb.ft_lp(wid())), uniform(tb.ft_lp(wid() + 1)), wlane(),
-        [&](int i) {
-          const uint32_t e = tb.ft(i);
-          return TermUpdate{(int)(e & 0xFFFF), tb.ft_coef(i) * P[e >> 16]};
-        },
+        [&](int i) { return TermEntry{tb.ft(i), 0u, tb.ft_coef(i)}; },
+        [&](const TermEntry& t) { return P[t.e >> 16]; },
+        [&](const TermEntry& t, double p) { return TermUpdate{(int)(t.e & 0xFFFF), t.c * p}; },
         [&](const TermUpdate& u) { lds_add(&xl[u.dst], u.v); });
     sync();
 #pragma unroll
@@ -277,26 +346,23 @@ struct WaveCell {
   // M = I - c J(yl) in the filled pattern (fill slots 0 off the diagonal), accumulated
   // contribution by contribution (one per lane).
   __device__ __forceinline__ void newton_matrix(double c) const {
-    for (int k = lane; k < m.R; k += G) {
-      const uint32_t v = tb.rx(k);
-      const int a = v & 0x3FF, b = (v >> 10) & 0x3FF, cc = (v >> 20) & 0x3FF;
-      const double kk = kc[k];
-      const int base = m.rx_pofs[k];
-      const double ya = a != 0x3FF ? yl[a] : 1.0, yb = b != 0x3FF ? yl[b] : 1.0,
-                   yc = cc != 0x3FF ? yl[cc] : 1.0;
-      if (a != 0x3FF) P[base] = kk * yb * yc;
-      if (b != 0x3FF) P[base + 1] = kk * ya * yc;
-      if (cc != 0x3FF) P[base + 2] = kk * ya * yb;
-    }
+    // partials of each reaction's rate with respect to each reactant occurrence
+    for_reactions([&](int k) { return TermEntry{tb.rx(k), (uint32_t)m.rx_pofs[k], kc[k]}; },
+                  [&](const TermEntry& t, const double (&y)[3]) {
+                    const double ya = yfac(t.e, 0, y[0]), yb = yfac(t.e, 1, y[1]),
+                                 yc = yfac(t.e, 2, y[2]);
+                    if ((t.e & 0x3FF) != 0x3FF) P[t.x] = t.c * yb * yc;
+                    if (((t.e >> 10) & 0x3FF) != 0x3FF) P[t.x + 1] = t.c * ya * yc;
+                    if (((t.e >> 20) & 0x3FF) != 0x3FF) P[t.x + 2] = t.c * ya * yb;
+                  });
     for (int s = lane; s < m.Z; s += G) M[s] = 0.0;
     sync();
     const double mc = -c;
-    for_terms<kTermBatch, kWave>(
+    for_terms_split<kTermBatch, kWave>(
         uniform(tb.jt_lp(wid())), uniform(tb.jt_lp(wid() + 1)), wlane(),
-        [&](int i) {
-          const uint32_t e = tb.jt(i);
-          return TermUpdate{(int)(e & 0xFFFF), mc * tb.jt_coef(i) * P[e >> 16]};
-        },
+        [&](int i) { return TermEntry{tb.jt(i), 0u, tb.jt_coef(i)}; },
+        [&](const TermEntry& t) { return P[t.e >> 16]; },
+        [&](const TermEntry& t, double p) { return TermUpdate{(int)(t.e & 0xFFFF), mc * t.c * p}; },
         [&](const TermUpdate& u) { lds_add(&M[u.dst], u.v); });
     sync();
     for (int t = lane; t < m.N; t += G) M[tb.dg(t)] += 1.0;
