@@ -385,25 +385,68 @@ struct WaveCell {
       M[d] = 1.0 / M[d];
     }
     sync();
-    for (int l = 0; l < L; ++l) {
-      const int2 r = level_range<kW>(tr, l, wid(), ltp);
-      for_terms<kLevelBatch, kWave>(
-          r.x, r.y, wlane(),
-          [&](int i) {
-            const uint2 e = tb.lt(i);
-            return TermUpdate{(int)(e.x & 0xFFFF), M[e.x >> 16] * M[e.y]};
-          },
-          [&](const TermUpdate& u) { lds_add(&M[u.dst], -u.v); });
-      sync();
-      const int flo = fhi;
-      fhi = level_ptr(fp, l + 2, [&](int k) { return tb.lf_lp(k); });
-      if (flo == fhi) continue;
-      for (int i = flo + lane; i < fhi; i += G) {
-        const uint32_t e = tb.lf(i);
+    if constexpr (kLevelBatch == 1) {
+      // Windows of kWin levels as in sweep(): a lane's first product-term entry and first
+      // finalize entry of every level of the window are read up front (an empty slot
+      // reads entry 0 and is not used).
+      constexpr int kWin = 8;
+      auto prod = [&](const uint2& e) { lds_add(&M[e.x & 0xFFFF], -(M[e.x >> 16] * M[e.y])); };
+      auto fin = [&](uint32_t e) {
         const int dst = e & 0xFFFF, pv = e >> 16;
         M[dst] = pv == 0xFFFF ? 1.0 / M[dst] : M[dst] * M[pv];
+      };
+      for (int l0 = 0; l0 < L; l0 += kWin) {
+        int2 r[kWin];
+        int fb[kWin + 1];
+        uint2 e[kWin];
+        uint32_t fe[kWin];
+        fb[0] = fhi;
+#pragma unroll
+        for (int u = 0; u < kWin; ++u) {
+          const bool on = l0 + u < L;
+          r[u] = on ? level_range<kW>(tr, l0 + u, wid(), ltp) : make_int2(0, 0);
+          fb[u + 1] = on ? level_ptr(fp, l0 + u + 2, [&](int k) { return tb.lf_lp(k); }) : fb[u];
+          const int i = r[u].x + wlane(), j = fb[u] + lane;
+          e[u] = tb.lt(i < r[u].y ? i : 0);
+          fe[u] = tb.lf(j < fb[u + 1] ? j : 0);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int u = 0; u < kWin; ++u) {
+          if (l0 + u >= L) break;
+          const int i = r[u].x + wlane();
+          if (i < r[u].y) prod(e[u]);
+          for (int k = i + kWave; k < r[u].y; k += kWave) prod(tb.lt(k));
+          sync();
+          if (fb[u] == fb[u + 1]) continue;
+          const int j = fb[u] + lane;
+          if (j < fb[u + 1]) fin(fe[u]);
+          for (int k = j + G; k < fb[u + 1]; k += G) fin(tb.lf(k));
+          sync();
+        }
+        fhi = fb[kWin];
       }
-      sync();
+    } else {
+      for (int l = 0; l < L; ++l) {
+        const int2 r = level_range<kW>(tr, l, wid(), ltp);
+        for_terms<kLevelBatch, kWave>(
+            r.x, r.y, wlane(),
+            [&](int i) {
+              const uint2 e = tb.lt(i);
+              return TermUpdate{(int)(e.x & 0xFFFF), M[e.x >> 16] * M[e.y]};
+            },
+            [&](const TermUpdate& u) { lds_add(&M[u.dst], -u.v); });
+        sync();
+        const int flo = fhi;
+        fhi = level_ptr(fp, l + 2, [&](int k) { return tb.lf_lp(k); });
+        if (flo == fhi) continue;
+        for (int i = flo + lane; i < fhi; i += G) {
+          const uint32_t e = tb.lf(i);
+          const int dst = e & 0xFFFF, pv = e >> 16;
+          M[dst] = pv == 0xFFFF ? 1.0 / M[dst] : M[dst] * M[pv];
+        }
+        sync();
+      }
     }
     for (int i = lane; i < tb.v.n_us; i += G) {
       const uint32_t e = tb.us(i);
@@ -451,6 +494,36 @@ struct WaveCell {
     const int nlev = kForward ? tb.v.n_sf_lev : tb.v.n_sb_lev;
     auto lp = [&](int l) { return kForward ? tb.sf_lp(l) : tb.sb_lp(l); };
     const LevelRange p = load_ranges<kW>(nlev, wid(), lp);
+    if constexpr (kLevelBatch == 1) {
+      // Levels of about one term per lane, in windows of kWin levels: a lane's first table
+      // entry of every level of the window is read up front (one round trip per window;
+      // an empty slot reads entry 0 and is not used), so a level then costs one LDS round
+      // trip for its data. Tables are read-only, and each level's data reads still follow
+      // the previous level's updates.
+      constexpr int kWin = 8;
+      auto ent = [&](int i) { return kForward ? tb.sf(i) : tb.sb(i); };
+      auto term = [&](const uint2& e) { lds_add(&xl[e.x & 0xFFFF], -(M[e.y] * xl[e.x >> 16])); };
+      for (int l0 = 0; l0 < nlev; l0 += kWin) {
+        int2 r[kWin];
+        uint2 e[kWin];
+#pragma unroll
+        for (int u = 0; u < kWin; ++u) {
+          r[u] = l0 + u < nlev ? level_range<kW>(p, l0 + u, wid(), lp) : make_int2(0, 0);
+          const int i = r[u].x + wlane();
+          e[u] = ent(i < r[u].y ? i : 0);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int u = 0; u < kWin; ++u) {
+          if (l0 + u >= nlev) break;
+          const int i = r[u].x + wlane();
+          if (i < r[u].y) term(e[u]);
+          for (int j = i + kWave; j < r[u].y; j += kWave) term(ent(j));
+          sync();
+        }
+      }
+      return;
+    }
     for (int l = 0; l < nlev; ++l) {
       const int2 r = level_range<kW>(p, l, wid(), lp);
       for_terms<kLevelBatch, kWave>(
