@@ -141,25 +141,24 @@ struct TermEntry {
 // updates are formed (make) and applied (scatter). Without the barriers the compiler,
 // short of registers, chains each entry load to its data read and each data read to its
 // use; with them a group costs one table round trip and one LDS round trip.
+// A group's last slots may fall past the end of the list: they load the lane's first
+// entry of the group (a valid one) and skip the update, so every group runs the same
+// three phases.
 template <int kU, int G, class Entry, class Load, class Make, class Scatter>
 __device__ __forceinline__ void for_terms_split(int lo, int hi, int lane, Entry entry, Load load,
                                                 Make make, Scatter scatter) {
-  int i = lo + lane;
-  for (; i + (kU - 1) * G < hi; i += kU * G) {
+  for (int i = lo + lane; i < hi; i += kU * G) {
     TermEntry e[kU];
 #pragma unroll
-    for (int u = 0; u < kU; ++u) e[u] = entry(i + u * G);
+    for (int u = 0; u < kU; ++u) e[u] = entry(i + u * G < hi ? i + u * G : i);
     __builtin_amdgcn_sched_barrier(0);
     double d[kU];
 #pragma unroll
     for (int u = 0; u < kU; ++u) d[u] = load(e[u]);
     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-    for (int u = 0; u < kU; ++u) scatter(make(e[u], d[u]));
-  }
-  for (; i < hi; i += G) {
-    const TermEntry e = entry(i);
-    scatter(make(e, load(e)));
+    for (int u = 0; u < kU; ++u)
+      if (i + u * G < hi) scatter(make(e[u], d[u]));
   }
 }
 
@@ -251,6 +250,8 @@ struct WaveCell {
   // Terms per lane issued together in the LU and sweep levels: levels of large mechanisms
   // hold several terms per lane, small ones rarely more than one.
   static constexpr int kLevelBatch = NPL >= 4 ? 4 : 1;
+  // Levels whose first table entries are read together (sweeps, LU).
+  static constexpr int kWindow = (G == kWave && NPL <= 2) ? 4 : 8;
   const DevMech& m;
   Tabs tb;
   double* M;
@@ -294,27 +295,21 @@ struct WaveCell {
 
   // Reactions k = lane, lane + G, ... in groups of kTermBatch per lane: table entries of a
   // group (entry), then its concentration reads, then use(entry, factors), with scheduling
-  // barriers between the phases as in for_terms_split.
+  // barriers between the phases and the end of the list handled as in for_terms_split.
   template <class Entry, class Use>
   __device__ __forceinline__ void for_reactions(Entry entry, Use use) const {
-    int k = lane;
-    for (; k + (kTermBatch - 1) * G < m.R; k += kTermBatch * G) {
+    for (int k = lane; k < m.R; k += kTermBatch * G) {
       TermEntry e[kTermBatch];
 #pragma unroll
-      for (int u = 0; u < kTermBatch; ++u) e[u] = entry(k + u * G);
+      for (int u = 0; u < kTermBatch; ++u) e[u] = entry(k + u * G < m.R ? k + u * G : k);
       __builtin_amdgcn_sched_barrier(0);
       double y[kTermBatch][3];
 #pragma unroll
       for (int u = 0; u < kTermBatch; ++u) yload(e[u].e, y[u]);
       __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-      for (int u = 0; u < kTermBatch; ++u) use(e[u], y[u]);
-    }
-    for (; k < m.R; k += G) {
-      const TermEntry e = entry(k);
-      double y[3];
-      yload(e.e, y);
-      use(e, y);
+      for (int u = 0; u < kTermBatch; ++u)
+        if (k + u * G < m.R) use(e[u], y[u]);
     }
   }
 
@@ -389,7 +384,7 @@ struct WaveCell {
       // Windows of kWin levels as in sweep(): a lane's first product-term entry and first
       // finalize entry of every level of the window are read up front (an empty slot
       // reads entry 0 and is not used).
-      constexpr int kWin = 8;
+      constexpr int kWin = kWindow;
       auto prod = [&](const uint2& e) { lds_add(&M[e.x & 0xFFFF], -(M[e.x >> 16] * M[e.y])); };
       auto fin = [&](uint32_t e) {
         const int dst = e & 0xFFFF, pv = e >> 16;
@@ -500,7 +495,7 @@ struct WaveCell {
       // an empty slot reads entry 0 and is not used), so a level then costs one LDS round
       // trip for its data. Tables are read-only, and each level's data reads still follow
       // the previous level's updates.
-      constexpr int kWin = 8;
+      constexpr int kWin = kWindow;
       auto ent = [&](int i) { return kForward ? tb.sf(i) : tb.sb(i); };
       auto term = [&](const uint2& e) { lds_add(&xl[e.x & 0xFFFF], -(M[e.y] * xl[e.x >> 16])); };
       for (int l0 = 0; l0 < nlev; l0 += kWin) {
