@@ -141,24 +141,25 @@ struct TermEntry {
 // updates are formed (make) and applied (scatter). Without the barriers the compiler,
 // short of registers, chains each entry load to its data read and each data read to its
 // use; with them a group costs one table round trip and one LDS round trip.
-// A group's last slots may fall past the end of the list: they load the lane's first
-// entry of the group (a valid one) and skip the update, so every group runs the same
-// three phases.
 template <int kU, int G, class Entry, class Load, class Make, class Scatter>
 __device__ __forceinline__ void for_terms_split(int lo, int hi, int lane, Entry entry, Load load,
                                                 Make make, Scatter scatter) {
-  for (int i = lo + lane; i < hi; i += kU * G) {
+  int i = lo + lane;
+  for (; i + (kU - 1) * G < hi; i += kU * G) {
     TermEntry e[kU];
 #pragma unroll
-    for (int u = 0; u < kU; ++u) e[u] = entry(i + u * G < hi ? i + u * G : i);
+    for (int u = 0; u < kU; ++u) e[u] = entry(i + u * G);
     __builtin_amdgcn_sched_barrier(0);
     double d[kU];
 #pragma unroll
     for (int u = 0; u < kU; ++u) d[u] = load(e[u]);
     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-    for (int u = 0; u < kU; ++u)
-      if (i + u * G < hi) scatter(make(e[u], d[u]));
+    for (int u = 0; u < kU; ++u) scatter(make(e[u], d[u]));
+  }
+  for (; i < hi; i += G) {
+    const TermEntry e = entry(i);
+    scatter(make(e, load(e)));
   }
 }
 
@@ -295,21 +296,27 @@ struct WaveCell {
 
   // Reactions k = lane, lane + G, ... in groups of kTermBatch per lane: table entries of a
   // group (entry), then its concentration reads, then use(entry, factors), with scheduling
-  // barriers between the phases and the end of the list handled as in for_terms_split.
+  // barriers between the phases as in for_terms_split.
   template <class Entry, class Use>
   __device__ __forceinline__ void for_reactions(Entry entry, Use use) const {
-    for (int k = lane; k < m.R; k += kTermBatch * G) {
+    int k = lane;
+    for (; k + (kTermBatch - 1) * G < m.R; k += kTermBatch * G) {
       TermEntry e[kTermBatch];
 #pragma unroll
-      for (int u = 0; u < kTermBatch; ++u) e[u] = entry(k + u * G < m.R ? k + u * G : k);
+      for (int u = 0; u < kTermBatch; ++u) e[u] = entry(k + u * G);
       __builtin_amdgcn_sched_barrier(0);
       double y[kTermBatch][3];
 #pragma unroll
       for (int u = 0; u < kTermBatch; ++u) yload(e[u].e, y[u]);
       __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-      for (int u = 0; u < kTermBatch; ++u)
-        if (k + u * G < m.R) use(e[u], y[u]);
+      for (int u = 0; u < kTermBatch; ++u) use(e[u], y[u]);
+    }
+    for (; k < m.R; k += G) {
+      const TermEntry e = entry(k);
+      double y[3];
+      yload(e.e, y);
+      use(e, y);
     }
   }
 
