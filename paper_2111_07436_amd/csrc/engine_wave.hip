@@ -21,7 +21,8 @@ int wave_max_waves(int n_state, int mode, int lanes) {
 
 int wave_resident_cells_per_cu(int n_state, int mode, int lanes) {
   if (lanes == 64) return wave_max_waves(n_state, mode, 64);
-  const int per_simd = (n_state + lanes - 1) / lanes <= 3 ? 2 : 1;   // see min_waves_per_simd
+  const int npl = (n_state + lanes - 1) / lanes;   // see min_waves_per_simd
+  const int per_simd = (lanes == 128 && npl <= 2 && kc_global(mode)) ? 3 : npl <= 3 ? 2 : 1;
   return 4 * per_simd / (lanes / 64);
 }
 

@@ -958,16 +958,17 @@ __device__ __forceinline__ Tabs stage_tables(const StageView& v, double* lds) {
 // (workgroups of up to 4 cells). In modes 3 and 4, up to 2 species per lane the kernel is
 // built for 168 registers (three wavefronts per SIMD, workgroups of up to 12 cells).
 // One workgroup per cell (G = 128 or 256): at most 256 VGPRs (two wavefronts per SIMD) up
-// to 3 species per lane, 512 beyond.
+// to 3 species per lane, 512 beyond; with G = 128 in modes 3 and 4, up to 2 species per
+// lane, 168 registers (three wavefronts per SIMD, six cells per CU).
 template <int NPL, int kMode, int G>
-constexpr bool occ3() { return G == kWave && NPL <= 2 && kc_global(kMode); }
+constexpr bool occ3() { return (G == kWave || G == 2 * kWave) && NPL <= 2 && kc_global(kMode); }
 template <int NPL, int kMode, int G>
 constexpr int max_threads() {
   return G > kWave ? G : kWave * (occ3<NPL, kMode, G>() ? 12 : NPL <= 3 ? 8 : 4);
 }
 template <int NPL, int kMode, int G>
 constexpr int min_waves_per_simd() {
-  return G > kWave ? (NPL <= 3 ? 2 : 1) : occ3<NPL, kMode, G>() ? 3 : 1;
+  return occ3<NPL, kMode, G>() ? 3 : G > kWave ? (NPL <= 3 ? 2 : 1) : 1;
 }
 
 // G = 64: blockDim.x = 64 * W, W wavefronts, one cell each; G > 64: blockDim.x = G, one
