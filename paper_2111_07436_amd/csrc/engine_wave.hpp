@@ -252,7 +252,7 @@ struct WaveCell {
   // hold several terms per lane, small ones rarely more than one.
   static constexpr int kLevelBatch = NPL >= 4 ? 4 : 1;
   // Levels whose first table entries are read together (sweeps, LU).
-  static constexpr int kWindow = (G == kWave && NPL <= 2) ? 4 : 8;
+  static constexpr int kWindow = (G == kWave && NPL <= 2) ? 2 : 8;
   const DevMech& m;
   Tabs tb;
   double* M;
