@@ -206,6 +206,7 @@ SolveParams make_params(double dt, double rtol, double atol, const camp_opts* o)
   sp.dt = dt;
   sp.rtol = rtol;
   sp.atol = atol;
+  sp.atol_call = atol;
   sp.max_order = (o && o->max_order >= 1 && o->max_order <= kMaxOrder) ? o->max_order : kMaxOrder;
   sp.max_steps = (o && o->max_steps > 0) ? o->max_steps : 100000;
   sp.newton_maxit = (o && o->newton_max_iter > 0) ? std::min(o->newton_max_iter, 16) : 4;

@@ -29,8 +29,16 @@ constexpr double kRestartFactor = 0.1;
 // Inequality constraint y >= 0 (CVODE's constraint option, Hindmarsh et al. 2005): a
 // converged step with a component below -1 in weighted-tolerance units is rejected and
 // the step cut by this factor. Without it, undershoots of fast species drive the
-// bimolecular terms unstable and the step size collapses.
+// bimolecular terms unstable and the step size collapses. The bound is one tolerance unit
+// below min(0, start value) (see start_value).
 constexpr double kConstraintFactor = 0.25;
+
+// The value a component starts the call from: an input at most one tolerance unit (of the
+// caller's tolerances) below zero, as a previous call's result may be, starts at zero;
+// any other input as given. The input row itself is not changed.
+__device__ __forceinline__ double start_value(double v, double rtol, double atol) {
+  return (v < 0.0 && -v <= atol + rtol * -v) ? 0.0 : v;
+}
 // Attempts per cell: 0 Newton with Jacobian reuse; 1 full Newton; 2 full Newton with the
 // absolute tolerance tightened by kRetryAtolFactor (a cell whose tiny, atol-controlled
 // species undershoot into the constraint over and over integrates at a tolerance at least

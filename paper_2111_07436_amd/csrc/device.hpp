@@ -76,6 +76,7 @@ struct DevEnv {
 
 struct SolveParams {
   double dt, rtol, atol, h_min, h_init, newton_tol;
+  double atol_call;   // the caller's atol (a retry attempt may tighten atol)
   int max_order, max_steps, newton_maxit;
   int full_newton;   // 1: full Newton from the start (no Jacobian reuse)
   // Persistent wavefront launches: queue position -> cell, used unless *order_bad != 0

@@ -211,7 +211,7 @@ __device__ void lane_init(const LaneCtx& C, int slot, int cell, int attempt, boo
   }
   const double* yrow = C.state + (size_t)cell * m.N;
   for (int t = 0; t < m.N; ++t) {
-    const double v = yrow[m.perm[t]];
+    const double v = start_value(yrow[m.perm[t]], C.sp.rtol, C.sp.atol_call);
     if (!isfinite(v)) ok = 0;
     L.y(t) = v;
     L.D(0, t) = v;
@@ -452,6 +452,16 @@ __device__ void lane_finish(const LaneCtx& C, int slot, int* new_step) {
   int neg = 0;
   for (int i = 0; i < m.N; ++i)
     if (L.y(i) * L.w(i) < -1.0) neg = 1;
+  if (neg) {
+    // a component that starts negative only counts if it is also more than one tolerance
+    // unit below its start value (the input row is unchanged until the cell ends)
+    const double* yin = C.state + (size_t)cell * m.N;
+    neg = 0;
+    for (int i = 0; i < m.N; ++i) {
+      const double lo = fmin(0.0, start_value(yin[m.perm[i]], C.sp.rtol, C.sp.atol_call));
+      if (L.y(i) * L.w(i) < -1.0 && (L.y(i) - lo) * L.w(i) < -1.0) neg = 1;
+    }
+  }
   if (neg) {
     S.st[slot].rejected++;
     L.rescale(q, kConstraintFactor);

@@ -589,7 +589,7 @@ __device__ __forceinline__ int integrate(const DevMech& m, double* yrow, const S
 #pragma unroll
   for (int i = 0; i < NPL; ++i) {
     const int t = lane + G * i;
-    const double v = t < N ? yrow[m.perm[t]] : 0.0;
+    const double v = t < N ? start_value(yrow[m.perm[t]], sp.rtol, sp.atol_call) : 0.0;
     if (t < N) {
       W.yl[t] = v;
       if (!isfinite(v)) bad = 1;
@@ -775,6 +775,20 @@ __device__ __forceinline__ int integrate(const DevMech& m, double* yrow, const S
 #pragma unroll
       for (int i = 0; i < NPL; ++i)
         if (lane + G * i < N && yv[i] * w[i] < -1.0) neg = 1;
+      if (W.any(neg)) {
+        // a component that starts negative only counts if it is also more than one
+        // tolerance unit below its start value (read back from the input row, which holds
+        // the input until the cell finishes)
+        neg = 0;
+#pragma unroll
+        for (int i = 0; i < NPL; ++i) {
+          const int tt = lane + G * i;
+          if (tt < N && yv[i] * w[i] < -1.0 &&
+              (yv[i] - fmin(0.0, start_value(yrow[m.perm[tt]], sp.rtol, sp.atol_call))) * w[i] <
+                  -1.0)
+            neg = 1;
+        }
+      }
       if (W.any(neg)) {
         cs.rejected++;
         rescale_hist(D, q, kConstraintFactor);
