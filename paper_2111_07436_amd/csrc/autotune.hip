@@ -176,12 +176,16 @@ int autotuned(camp_mech* mh, const DevMech& dm, int n_cells, double* d_state,
     return CAMP_OK;
   }
 
-  // Trial on a copy of the first cells of this call.
+  // Trial on a copy of the first cells of this call: enough cells for several per resident
+  // slot. Then, for a larger call, the three fastest launches run again on four times as
+  // many cells: near the trial size the lowest per-cell latency wins (the last cells finish
+  // alone), while a large call is decided by throughput.
   const int cus = n_cus_dev();
-  const int trial = std::min(n_cells, std::max(4096, cus * 32));
-  const size_t sbytes = sizeof(double) * (size_t)trial * dm.N;
+  const int trial = std::min(n_cells, std::max(4096, cus * 64));
+  const int big = std::min(n_cells, 4 * trial);
+  const size_t sbytes = sizeof(double) * (size_t)big * dm.N;
   char* buf = nullptr;
-  hipError_t e = hipMallocAsync((void**)&buf, 2 * sbytes + 4 * (size_t)trial + 256, stream);
+  hipError_t e = hipMallocAsync((void**)&buf, 2 * sbytes + 4 * (size_t)big + 256, stream);
   if (e != hipSuccess) return hip_fail(e, "hipMallocAsync(autotune)");
   double* src = reinterpret_cast<double*>(buf);
   double* work = reinterpret_cast<double*>(buf + sbytes);
@@ -196,30 +200,49 @@ int autotuned(camp_mech* mh, const DevMech& dm, int n_cells, double* d_state,
   camp_opts topts{};
   if (opts) topts = *opts;
   topts.cell_order = nullptr;
+  // up to `reps` timed runs of launch t on identical copies of the first n cells (min); a
+  // launch far slower than `bound` is not run again. Returns a negative time if t cannot
+  // be launched for this mechanism.
+  auto timed = [&](const Tuning& t, int n, int reps, float bound) -> float {
+    float best_ms = 1e30f;
+    for (int rep = 0; rep < reps; ++rep) {
+      if (hipMemcpyAsync(work, src, sizeof(double) * (size_t)n * dm.N, hipMemcpyDeviceToDevice,
+                         stream) != hipSuccess)
+        return -1.f;
+      hipEventRecord(a, stream);
+      int rc = solve_device_tuned(mh, dm, n, work, d_env, sp, &topts, st, nullptr, stream, t);
+      hipEventRecord(b, stream);
+      if (hipEventSynchronize(b) != hipSuccess) rc = CAMP_EDEVICE;
+      if (rc != CAMP_OK) return -1.f;
+      float ms = 0.f;
+      hipEventElapsedTime(&ms, a, b);
+      best_ms = std::min(best_ms, ms);
+      if (ms > 2.0f * bound) break;
+    }
+    return best_ms;
+  };
+  std::vector<Tuning> ranked;
   if (e == hipSuccess) {
     for (Tuning t : candidates(dm)) {
-      // up to two timed runs on identical copies (min); a candidate far slower than the
-      // best so far is not run again
-      float best_ms = 1e30f;
-      int rc = CAMP_OK;
-      for (int rep = 0; rep < 2 && rc == CAMP_OK; ++rep) {
-        if (hipMemcpyAsync(work, src, sbytes, hipMemcpyDeviceToDevice, stream) != hipSuccess) {
-          rc = CAMP_EDEVICE;
-          break;
-        }
-        hipEventRecord(a, stream);
-        rc = solve_device_tuned(mh, dm, trial, work, d_env, sp, &topts, st, nullptr, stream, t);
-        hipEventRecord(b, stream);
-        if (hipEventSynchronize(b) != hipSuccess) rc = CAMP_EDEVICE;
-        float ms = 0.f;
-        if (rc == CAMP_OK) hipEventElapsedTime(&ms, a, b);
-        best_ms = std::min(best_ms, ms);
-        if (ms > 2.0 * best.ms) break;
-      }
-      if (rc != CAMP_OK) continue;   // candidate not launchable for this mechanism
-      t.ms = best_ms;
+      const float ms = timed(t, trial, 2, (float)best.ms);
+      if (ms < 0.f) continue;   // candidate not launchable for this mechanism
+      t.ms = ms;
+      ranked.push_back(t);
       if (t.ms < best.ms) best = t;
     }
+  }
+  if (big > trial && ranked.size() > 1) {
+    std::sort(ranked.begin(), ranked.end(),
+              [](const Tuning& x, const Tuning& y) { return x.ms < y.ms; });
+    ranked.resize(std::min<size_t>(ranked.size(), 3));
+    best.ms = 1e30;
+    for (Tuning t : ranked) {
+      const float ms = timed(t, big, 1, 1e30f);
+      if (ms < 0.f) continue;
+      t.ms = ms;
+      if (t.ms < best.ms) best = t;
+    }
+    if (best.ms >= 1e30) best = ranked.front();
   }
   if (a) hipEventDestroy(a);
   if (b) hipEventDestroy(b);

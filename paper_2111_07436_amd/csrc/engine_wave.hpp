@@ -141,26 +141,30 @@ struct TermEntry {
 // updates are formed (make) and applied (scatter). Without the barriers the compiler,
 // short of registers, chains each entry load to its data read and each data read to its
 // use; with them a group costs one table round trip and one LDS round trip.
+// One group of kU terms i, i + G, ... of for_terms_split.
+template <int kU, int G, class Entry, class Load, class Make, class Scatter>
+__device__ __forceinline__ void term_group(int i, Entry entry, Load load, Make make,
+                                           Scatter scatter) {
+  TermEntry e[kU];
+#pragma unroll
+  for (int u = 0; u < kU; ++u) e[u] = entry(i + u * G);
+  __builtin_amdgcn_sched_barrier(0);
+  double d[kU];
+#pragma unroll
+  for (int u = 0; u < kU; ++u) d[u] = load(e[u]);
+  __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+  for (int u = 0; u < kU; ++u) scatter(make(e[u], d[u]));
+}
+
+// The remainder after the groups of kU runs as groups of 2, then single terms.
 template <int kU, int G, class Entry, class Load, class Make, class Scatter>
 __device__ __forceinline__ void for_terms_split(int lo, int hi, int lane, Entry entry, Load load,
                                                 Make make, Scatter scatter) {
   int i = lo + lane;
-  for (; i + (kU - 1) * G < hi; i += kU * G) {
-    TermEntry e[kU];
-#pragma unroll
-    for (int u = 0; u < kU; ++u) e[u] = entry(i + u * G);
-    __builtin_amdgcn_sched_barrier(0);
-    double d[kU];
-#pragma unroll
-    for (int u = 0; u < kU; ++u) d[u] = load(e[u]);
-    __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-    for (int u = 0; u < kU; ++u) scatter(make(e[u], d[u]));
-  }
-  for (; i < hi; i += G) {
-    const TermEntry e = entry(i);
-    scatter(make(e, load(e)));
-  }
+  for (; i + (kU - 1) * G < hi; i += kU * G) term_group<kU, G>(i, entry, load, make, scatter);
+  for (; i + G < hi; i += 2 * G) term_group<2, G>(i, entry, load, make, scatter);
+  for (; i < hi; i += G) term_group<1, G>(i, entry, load, make, scatter);
 }
 
 constexpr int kTermBatch = 4;
@@ -297,27 +301,26 @@ struct WaveCell {
   // Reactions k = lane, lane + G, ... in groups of kTermBatch per lane: table entries of a
   // group (entry), then its concentration reads, then use(entry, factors), with scheduling
   // barriers between the phases as in for_terms_split.
+  template <int kU, class Entry, class Use>
+  __device__ __forceinline__ void reaction_group(int k, Entry entry, Use use) const {
+    TermEntry e[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) e[u] = entry(k + u * G);
+    __builtin_amdgcn_sched_barrier(0);
+    double y[kU][3];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) yload(e[u].e, y[u]);
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int u = 0; u < kU; ++u) use(e[u], y[u]);
+  }
   template <class Entry, class Use>
   __device__ __forceinline__ void for_reactions(Entry entry, Use use) const {
     int k = lane;
-    for (; k + (kTermBatch - 1) * G < m.R; k += kTermBatch * G) {
-      TermEntry e[kTermBatch];
-#pragma unroll
-      for (int u = 0; u < kTermBatch; ++u) e[u] = entry(k + u * G);
-      __builtin_amdgcn_sched_barrier(0);
-      double y[kTermBatch][3];
-#pragma unroll
-      for (int u = 0; u < kTermBatch; ++u) yload(e[u].e, y[u]);
-      __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-      for (int u = 0; u < kTermBatch; ++u) use(e[u], y[u]);
-    }
-    for (; k < m.R; k += G) {
-      const TermEntry e = entry(k);
-      double y[3];
-      yload(e.e, y);
-      use(e, y);
-    }
+    for (; k + (kTermBatch - 1) * G < m.R; k += kTermBatch * G)
+      reaction_group<kTermBatch>(k, entry, use);
+    for (; k + G < m.R; k += 2 * G) reaction_group<2>(k, entry, use);
+    for (; k < m.R; k += G) reaction_group<1>(k, entry, use);
   }
 
   // P[k] = r_k from yl; then f for owned species, accumulated term by term (one term per
