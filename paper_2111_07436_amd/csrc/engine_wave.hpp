@@ -939,8 +939,9 @@ __device__ __forceinline__ void solve_one_cell(const DevMech& m, const DevEnv& e
 //   3  tables from global memory and rate constants in a global per-wavefront scratch
 //      (persistent launches only), for mechanisms whose per-cell LDS is the occupancy limit
 //   4  core index tables staged in LDS and rate constants in the global scratch
-// In modes 3 and 4 a mechanism of at most 128 state variables runs a kernel built for
-// three wavefronts per SIMD (at most 168 registers), with up to 12 cells per workgroup.
+// In modes 3 and 4, cells of at most two species per lane (up to 128 state variables on one
+// wavefront, up to 256 on two) run a kernel built for three wavefronts per SIMD (at most 168
+// registers): up to 12 one-wavefront cells per workgroup, or six two-wavefront cells per CU.
 __host__ __device__ constexpr bool kc_global(int mode) { return mode >= 3; }
 
 // LDS doubles of one cell: M [Z], y [N], x [N], partials/rates, 8 doubles of group
