@@ -97,7 +97,9 @@ def calibrate_copy(mib=1024, reps=5):
 
 
 def algorithmic_flops(info, mech, stats_mean):
-    """FP64 flops one cell's solve needs, from its counters (see the flop table in the design doc)."""
+    """FP64 flops one cell's solve needs: the per-cell counters (forcing evaluations, Jacobians,
+    LU factorizations, Newton iterations, steps) times the operation counts of the compiled
+    mechanism (products, terms, contributions, LU pairs and the filled pattern)."""
     N, Z = info["n_state"], info["nnz_fill"]
     sum_nr_nr1 = 0
     for r in mech.reactions:
@@ -342,8 +344,8 @@ def main():
                     help="only run a 1 GiB device copy (for scaling rocprofv3 byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU: every cell is independent, so more GPUs shard the cells "
-              "with no exchange (see DESIGN.md); only --gpus 1 is supported in this build.",
+        print("bench.py measures one GPU: every cell is independent, so several GPUs would each "
+              "take a share of the cells with no exchange; only --gpus 1 is supported.",
               file=sys.stderr)
         sys.exit(2)
     import torch

@@ -20,5 +20,5 @@ It is a plain, slow, obviously correct implementation of what the method compute
 * ``solve``   -- per-cell driver tying these together.
 
 Parity of the full configurations against the paper is unpinned (the paper prints no
-result values); every function here is pinned by the tests listed in the design doc.
+result values); every function here is pinned by the CPU tests in tests/test_oracle_*.py.
 """

@@ -19,7 +19,7 @@ published backward-difference (quasi-constant step) form of BDF of Shampine & Re
   q and q+1 and take the order allowing the largest step (ties keep the order).
 * The last step is shortened to land exactly on the end of the host step.
 
-Reading choices where the paper is silent (recorded in the design doc): Newton tolerance 0.03
+Reading choices where the paper is silent: Newton tolerance 0.03
 of the error tolerance, at most 4 Newton iterations, safety 0.9, step factor in
 [0.2, 5] after an accept (<= 1 after a reject), Newton failure halves h, initial step
 from the starting-step heuristic of Hairer, Norsett & Wanner (Vol. I, Sect. II.4).

@@ -16,7 +16,7 @@ def log(msg):
 
 
 def parity_errors(y_gpu, y_ref, floor=1e-12):
-    """Relative error where |y_ref| >= floor, absolute error elsewhere (spec metric)."""
+    """Relative error where |y_ref| >= floor, absolute error elsewhere (the parity gate)."""
     big = np.abs(y_ref) >= floor
     rel = np.zeros_like(y_ref)
     rel[big] = np.abs(y_gpu[big] - y_ref[big]) / np.abs(y_ref[big])

@@ -1,4 +1,4 @@
-"""Served requests (a12): continuous batching keeps every result identical to a solo solve.
+"""Served requests: continuous batching keeps every result identical to a solo solve.
 
 Requests of different sizes on two resident mechanisms (the gas mechanism and the
 multiphase one) are submitted together; each result must equal, bit for bit, the result

@@ -1,6 +1,7 @@
-"""End-to-end parity of every engine against the oracle (a2-a8), through the C ABI.
+"""End-to-end parity of every engine against the oracle (forcing, Jacobian, LU, solves, BDF
+control and the fused kernels), through the C ABI.
 
-Gate (spec metric, reading C-6 in the design doc): with the GPU at rtol 1e-8 / atol 1e-18
+Gate: with the GPU at rtol 1e-8 / atol 1e-18
 and the oracle at rtol 1e-10 / atol 1e-20, every species with |y_ref| >= 1e-12 mol m^-3
 agrees to 1e-4 relative and every species below that floor to 1e-12 absolute.
 """

@@ -1,4 +1,5 @@
-"""Kernel-level parity of the hot-path steps (a1-a5) against the oracle, through the C ABI.
+"""Kernel-level parity of the hot-path steps (rate constants, forcing, Newton matrix, LU,
+triangular solves) against the oracle, through the C ABI.
 
 Each step runs the fused engine's device code on row-major inputs; the oracle computes the
 same quantity densely in FP64. Bars: rate constants and forcing to a few ulps of their

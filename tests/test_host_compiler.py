@@ -1,4 +1,4 @@
-"""Host mechanism compiler (a0) through the C ABI, checked against the oracle (CPU).
+"""Host mechanism compiler through the C ABI, checked against the oracle (CPU).
 
 The C++ compiler's expansion, Jacobian pattern and symbolic LU fill must equal the
 oracle's brute-force constructions bit for bit (integer work).
