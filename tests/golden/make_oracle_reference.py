@@ -14,6 +14,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
 sys.path.insert(0, ROOT)
 
@@ -21,11 +23,12 @@ from oracle.solve import oracle_solve_parallel  # noqa: E402
 from paper_2111_07436_amd import workloads as W  # noqa: E402
 
 RTOL, ATOL = 1e-10, 1e-20
-# (n_cells the workload is generated with, sampled cells): the full-size C3 workload, and a
-# 4096-cell slice of the C5 configuration (its own seeded draws at that size).
+# (n_cells the workload is generated with, sampled cells), both at full size: the first and
+# last cells, cells spread evenly over the rest, and zero-aerosol cells (C3 cells 1 and 5, C5 cells
+# 2 and 3 have no aerosol mass in the seeded draws).
 SAMPLES = {
-    "c3": (100_000, [0, 1, 2, 50_000, 99_999]),
-    "c5": (4096, [0, 4095]),
+    "c3": (100_000, [0, 1, 2, 5, 25_000, 50_000, 75_000, 99_999]),
+    "c5": (500_000, [0, 2, 3] + [int(c) for c in np.linspace(38_461, 461_538, 12)] + [499_999]),
 }
 
 
@@ -34,7 +37,8 @@ def make(name, processes):
     wl = W.make_workload(name, n_cells=n)
     t = time.time()
     y, st = oracle_solve_parallel(wl.mech, wl.env, wl.y0, wl.dt, wl.n_calls, RTOL, ATOL, cells, processes)
-    out = {"workload": name, "n_cells": n, "cells": cells, "rtol": RTOL, "atol": ATOL,
+    zero = [int(c) for c in cells if np.all(wl.env.mass[c] == 0.0)] if wl.env.mass.size else []
+    out = {"workload": name, "n_cells": n, "cells": cells, "zero_aerosol_cells": zero, "rtol": RTOL, "atol": ATOL,
            "n_calls": wl.n_calls, "dt": wl.dt, "status": [int(s) for s in st],
            "y": [[float(v) for v in row] for row in y], "oracle_seconds": time.time() - t}
     path = os.path.join(os.path.dirname(os.path.abspath(__file__)), f"oracle_{name}.json")

@@ -192,34 +192,12 @@ def test_self_consistency_c2():
     assert np.max(np.abs(a - b)[big] / np.abs(b[big])) < 1e-7
 
 
-def test_history_rescale_is_exact_for_polynomials():
-    # differences of a degree-q polynomial at spacing h, rescaled to rho*h, equal the
-    # differences computed directly at spacing rho*h
-    q, h, rho = 4, 0.3, 0.37
-    c = np.array([0.5, -1.2, 0.7, 0.25, -0.05])
-    p = np.polynomial.Polynomial(c)
-
-    def diffs(step):
-        vals = np.array([p(-m * step) for m in range(q + 1)])
-        D = [vals[0]]
-        cur = vals
-        for _ in range(q):
-            cur = cur[:-1] - cur[1:]
-            D.append(cur[0])
-        return np.array(D)
-
-    D = np.zeros((B.MAX_ORDER + 3, 1))
-    D[:q + 1, 0] = diffs(h)
-    B.rescale_history(D, q, rho)
-    assert np.allclose(D[:q + 1, 0], diffs(rho * h), rtol=1e-12, atol=1e-14)
-
-
 def test_failure_statuses():
     mech = mechs.first_order(1e-2)
     y0 = [1e-8, 0.0]
     _, st, _ = solve1(mech, y0, 1000.0, rtol=1e-8, atol=1e-20, max_steps=1)
     assert st == B.ST_MAX_STEPS
-    _, st, _ = solve1(mech, y0, 1000.0, rtol=1e-8, atol=1e-20, h_min_frac=2.0)
+    _, st, _ = solve1(mech, y0, 1000.0, rtol=1e-8, atol=1e-20, h_min=2000.0)
     assert st == B.ST_H_MIN
     _, st, _ = solve1(mech, y0, 1000.0, rtol=1e-8, atol=0.0)
     assert st == B.ST_NONFINITE
