@@ -45,7 +45,7 @@ typedef enum {
 enum {
   CAMP_CELL_OK = 0,
   CAMP_CELL_MAX_STEPS = 1,    /* more step attempts than opts.max_steps            */
-  CAMP_CELL_H_MIN = 2,        /* step size fell below opts.h_min                   */
+  CAMP_CELL_H_MIN = 2,        /* step below opts.h_min or the roundoff floor of t  */
   CAMP_CELL_ERR_FAIL = 3,     /* 10 consecutive local error test failures          */
   CAMP_CELL_NEWTON_FAIL = 4,  /* 10 consecutive Newton convergence failures        */
   CAMP_CELL_NONFINITE = 5     /* non-finite rate constant, forcing or weight       */
@@ -138,6 +138,7 @@ typedef struct {
   int n_partials;       /* sum over reactions of reactant occurrences                */
   int n_terms;          /* forcing terms (species x reaction with nonzero net coef)  */
   int n_jac_contrib;    /* Jacobian contributions                                    */
+  int tail_k;           /* size of the dense trailing block of the filled pattern        */
 } camp_mech_info_t;
 
 int camp_mech_info(const camp_mech* mech, camp_mech_info_t* info);
@@ -148,6 +149,25 @@ int camp_mech_info(const camp_mech* mech, camp_mech_info_t* info);
  *                  order, ascending); value slot s of the device matrices is CSR entry s.
  *  pattern0[Z]   : 1 if the slot is in the unfilled pattern, 0 if it is fill. */
 int camp_mech_export(const camp_mech* mech, int* perm, int* row_ptr, int* col, int* pattern0);
+
+/* The fused kernel's table layout for lanes_per_cell (64, 128 or 256): dense tail size,
+ * dependency levels of the forward sweep, backward sweep and factorization it runs (the
+ * Gauss-Jordan steps of the tail come on top of lu_levels), and bytes of its table block.
+ * Any output pointer may be NULL. */
+int camp_mech_layout_info(const camp_mech* mech, int lanes_per_cell, int* tail_k, int* fwd_levels,
+                          int* bwd_levels, int* lu_levels, int* staged_bytes);
+
+/* Validation: runs the fused kernel's factor-and-solve table program on the host, in
+ * order, for one matrix (paper Sect. 2.4.1: the sparse direct solve of each Newton
+ * iteration). m[Z] holds a Newton matrix in the slot order of camp_mech_export and is
+ * overwritten with the factors (the pivot reciprocals, row-scaled U and, with the dense
+ * tail, the inverse of the trailing block's Schur complement); x[N] holds the right-hand
+ * side in elimination order (position t is state perm[t]) and is overwritten with the
+ * solution. lanes_per_cell (64, 128 or 256) selects the term-list layout; dense_tail = 0
+ * selects the plain layout of the single-step entry points (64 only). Host memory only.
+ * Returns CAMP_ESOLVE on a zero or non-finite pivot, CAMP_EINVAL on bad arguments. */
+int camp_emulate_factor_solve(const camp_mech* mech, int lanes_per_cell, int dense_tail,
+                              double* m, double* x);
 
 void camp_mech_free(camp_mech* mech);
 
@@ -180,7 +200,8 @@ typedef struct {
   int max_order;        /* 1..5 (default 5)                                           */
   int max_steps;        /* step attempts per cell per call (default 100000)           */
   int newton_max_iter;  /* default 4                                                  */
-  double h_min;         /* absolute minimum step, s (default 1e-14 * dt)              */
+  double h_min;         /* absolute minimum step, s (default 0: only the roundoff floor,*/
+                        /* a step too small to change the time reached)               */
   double h_init;        /* > 0: initial step, s (default: starting-step heuristic)    */
   int engine;           /* CAMP_ENGINE_*                                              */
   int wg_per_cu;        /* FUSED_WAVE persistent grid: workgroups per CU, 0 = auto     */
@@ -235,6 +256,31 @@ int camp_solve(camp_mech* mech, int n_cells, double* state, const camp_env* env,
 int camp_solve_device(camp_mech* mech, int n_cells, double* d_state, const camp_env* d_env,
                       double dt, double rtol, double atol, const camp_opts* opts,
                       int* d_cell_status, camp_cell_stats* d_cell_stats, void* stream);
+
+/* --- Plans: one device solve captured once as a HIP graph and replayed. For a host model
+ *     that calls the solver every time step on the same device arrays (paper Sect. 2.4.2:
+ *     set the environment, solve, read the state back, every step): the launch sequence of
+ *     the fused wavefront engine (queue reset, cell-order check, persistent kernel) is
+ *     resolved (autotuner trials included), given its own scratch and captured once; each
+ *     replay then costs one graph launch. --- */
+typedef struct camp_plan camp_plan;
+
+/* Same arguments as camp_solve_device; the pointers (device memory) are fixed in the plan
+ * and read at every replay, so they must stay valid until camp_plan_free. Only the fused
+ * wavefront engine is captured: engine AUTO (which must resolve to it) or FUSED_WAVE, else
+ * CAMP_EINVAL. The plan owns its scratch: replays of different plans may overlap, replays of
+ * one plan on several streams at once race. Errors: CAMP_EINVAL, CAMP_ENOMEM, CAMP_EDEVICE. */
+int camp_plan_create(camp_mech* mech, int n_cells, double* d_state, const camp_env* d_env,
+                     double dt, double rtol, double atol, const camp_opts* opts,
+                     int* d_cell_status, camp_cell_stats* d_cell_stats, void* stream,
+                     camp_plan** out);
+
+/* Replays the captured solve on `stream` (stream-ordered; results as camp_solve_device).
+ * The current device must be the plan's. */
+int camp_plan_launch(camp_plan* plan, void* stream);
+
+/* Waits for the plan's device, then releases the graph and its scratch. NULL is ignored. */
+void camp_plan_free(camp_plan* plan);
 
 /* --- Individual hot-path steps on device arrays (validation and composition). All
  *     per-cell arrays are row-major [cells][...] device memory. --- */

@@ -58,7 +58,7 @@ class MechInfo(C.Structure):
                 ("n_rxn_expanded", C.c_int), ("n_external", C.c_int), ("nnz_pattern", C.c_int),
                 ("nnz_fill", C.c_int), ("lu_pairs", C.c_longlong), ("lu_levels", C.c_int),
                 ("fwd_levels", C.c_int), ("bwd_levels", C.c_int), ("n_partials", C.c_int),
-                ("n_terms", C.c_int), ("n_jac_contrib", C.c_int)]
+                ("n_terms", C.c_int), ("n_jac_contrib", C.c_int), ("tail_k", C.c_int)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -91,6 +91,8 @@ _sig = {
     "camp_mech_info": (C.c_int, [_P, C.POINTER(MechInfo)]),
     "camp_mech_export": (C.c_int, [_P, _P, _P, _P, _P]),
     "camp_mech_free": (None, [_P]),
+    "camp_emulate_factor_solve": (C.c_int, [_P, C.c_int, C.c_int, _P, _P]),
+    "camp_mech_layout_info": (C.c_int, [_P, C.c_int, _P, _P, _P, _P, _P]),
     "camp_solve": (C.c_int, [_P, C.c_int, _P, C.POINTER(Env), C.c_double, C.c_double, C.c_double,
                              C.POINTER(Opts), _P, _P]),
     "camp_solve_device": (C.c_int, [_P, C.c_int, _P, C.POINTER(Env), C.c_double, C.c_double,
@@ -101,6 +103,10 @@ _sig = {
     "camp_lu_factor_device": (C.c_int, [_P, C.c_int, _P, _P]),
     "camp_lu_solve_device": (C.c_int, [_P, C.c_int, _P, _P, _P]),
     "camp_count_failed": (C.c_int, [C.c_int, _P, C.POINTER(C.c_int), _P]),
+    "camp_plan_create": (C.c_int, [_P, C.c_int, _P, C.POINTER(Env), C.c_double, C.c_double,
+                                   C.c_double, C.POINTER(Opts), _P, _P, _P, C.POINTER(_P)]),
+    "camp_plan_launch": (C.c_int, [_P, _P]),
+    "camp_plan_free": (None, [_P]),
     "camp_serve_create": (C.c_int, [C.c_longlong, C.c_int, C.POINTER(_P)]),
     "camp_serve_submit": (C.c_int, [_P, _P, C.c_int, _P, C.POINTER(Env), C.c_double, C.c_double,
                                     C.c_double, C.POINTER(Opts), _P, C.POINTER(C.c_longlong)]),
@@ -232,6 +238,22 @@ class Mech:
                                      p0.ctypes.data))
         return perm, rp, col, p0
 
+    def layout_info(self, lanes_per_cell):
+        """camp_mech_layout_info: dict of the fused kernel's table layout."""
+        v = [C.c_int(0) for _ in range(5)]
+        _check(_lib.camp_mech_layout_info(self.h, int(lanes_per_cell), *[C.byref(a) for a in v]))
+        return dict(zip(["tail_k", "fwd_levels", "bwd_levels", "lu_levels", "staged_bytes"],
+                        [a.value for a in v]))
+
+    def emulate_factor_solve(self, m, b, lanes_per_cell=64, dense_tail=True):
+        """camp_emulate_factor_solve on host arrays: returns (factors, x) for a Newton matrix
+        m[Z] (slot order) and right-hand side b[N] (elimination order)."""
+        m = np.ascontiguousarray(m, dtype=np.float64).copy()
+        x = np.ascontiguousarray(b, dtype=np.float64).copy()
+        _check(_lib.camp_emulate_factor_solve(self.h, int(lanes_per_cell), int(bool(dense_tail)),
+                                              m.ctypes.data, x.ctypes.data))
+        return m, x
+
     # ------------------------------------------------------------------ host solve
     def solve(self, env, y, dt, rtol, atol, opts: Optional[Opts] = None, stats=False):
         """camp_solve on host arrays; returns (y_out, status, stats or None)."""
@@ -291,6 +313,41 @@ class Mech:
     def lu_solve(self, d_lu, d_b):
         _check(_lib.camp_lu_solve_device(self.h, d_b.shape[0], _ptr(d_lu), _ptr(d_b), _stream()))
         return d_b
+
+
+class Plan:
+    """A device solve captured once as a HIP graph (wraps camp_plan); the tensors are fixed
+    in the plan and read at every replay."""
+
+    def __init__(self, mech: Mech, denv: DeviceEnv, d_state, dt, rtol, atol,
+                 opts: Optional[Opts] = None, d_status=None, d_stats=None):
+        import torch
+        n = d_state.shape[0]
+        if d_status is None:
+            d_status = torch.empty(n, dtype=torch.int32, device=d_state.device)
+        self._keep = (mech, denv, d_state, d_status, d_stats, opts)
+        self.d_status = d_status
+        e = denv.c_env()
+        h = C.c_void_p()
+        _check(_lib.camp_plan_create(mech.h, n, _ptr(d_state), C.byref(e), dt, rtol, atol,
+                                     None if opts is None else C.byref(opts), _ptr(d_status),
+                                     _ptr(d_stats), _stream(), C.byref(h)))
+        self.h = h
+
+    def launch(self):
+        _check(_lib.camp_plan_launch(self.h, _stream()))
+        return self.d_status
+
+    def close(self):
+        if getattr(self, "h", None):
+            _lib.camp_plan_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def count_failed(d_status):

@@ -75,9 +75,10 @@ int upload(camp_mech* mh, int device, DeviceTables& out) {
          o_bwt = add(C.bwd_tasks.data(), sizeof(Task) * C.bwd_tasks.size()),
          o_lup = add(lup.data(), 4 * lup.size()), o_fwp = add(fwp.data(), 4 * fwp.size()),
          o_bwp = add(bwp.data(), 4 * bwp.size()),
-         o_stage[3] = {add(mh->stage[0].bytes.data(), mh->stage[0].bytes.size()),
+         o_stage[4] = {add(mh->stage[0].bytes.data(), mh->stage[0].bytes.size()),
                        add(mh->stage[1].bytes.data(), mh->stage[1].bytes.size()),
-                       add(mh->stage[2].bytes.data(), mh->stage[2].bytes.size())};
+                       add(mh->stage[2].bytes.data(), mh->stage[2].bytes.size()),
+                       add(mh->stage[3].bytes.data(), mh->stage[3].bytes.size())};
 
   std::vector<char> host(total, 0);
   for (auto& it : items)
@@ -127,7 +128,7 @@ int upload(camp_mech* mh, int device, DeviceTables& out) {
   d.lu_pair = (const int2*)(b + o_lup);
   d.fwd_pair = (const int2*)(b + o_fwp);
   d.bwd_pair = (const int2*)(b + o_bwp);
-  for (int v = 0; v < 3; ++v) {
+  for (int v = 0; v < 4; ++v) {
     const StageBlock& sb = mh->stage[v];
     StageView& w = d.sv[v];
     w = StageView{};
@@ -158,12 +159,29 @@ int upload(camp_mech* mh, int device, DeviceTables& out) {
     w.so_ft_lp = sb.off_ft_lp;
     w.so_jt_lp = sb.off_jt_lp;
     w.wave_lists = sb.wave_lists;
+    w.n_lu_lev = sb.n_lu_lev;
+    w.tail_k = sb.tail_k;
+    w.tail_s = sb.tail_s;
+    w.so_tail = sb.off_tail;
+    w.so_tail_lp = sb.off_tail_lp;
+    w.n_tail = sb.n_tail;
   }
   d.stage = d.sv[0].base;
   out.device = device;
   out.blob = blob;
   out.bytes = total;
   return CAMP_OK;
+}
+
+}  // namespace
+
+// Device-resident tables of `mh` for the current device, if already uploaded (else null).
+const DevMech* resident_if_uploaded(camp_mech* mh) {
+  int device = 0;
+  if (hipGetDevice(&device) != hipSuccess) return nullptr;
+  std::lock_guard<std::mutex> g(mh->mu);
+  auto it = mh->dev.find(device);
+  return it == mh->dev.end() ? nullptr : &it->second.dm;
 }
 
 // Device-resident tables of `mh` for the current device (uploaded on first use).
@@ -210,7 +228,7 @@ SolveParams make_params(double dt, double rtol, double atol, const camp_opts* o)
   sp.max_order = (o && o->max_order >= 1 && o->max_order <= kMaxOrder) ? o->max_order : kMaxOrder;
   sp.max_steps = (o && o->max_steps > 0) ? o->max_steps : 100000;
   sp.newton_maxit = (o && o->newton_max_iter > 0) ? std::min(o->newton_max_iter, 16) : 4;
-  sp.h_min = (o && o->h_min > 0) ? o->h_min : 1e-14 * dt;
+  sp.h_min = (o && o->h_min > 0) ? o->h_min : 0.0;
   sp.h_init = (o && o->h_init > 0) ? o->h_init : 0.0;
   sp.newton_tol = 0.1;
   sp.full_newton = (o && o->full_newton) ? 1 : 0;
@@ -234,7 +252,6 @@ int n_cus() {
   return cus;
 }
 
-}  // namespace
 
 void set_error(const std::string& msg) { g_err = msg; }
 
@@ -243,11 +260,97 @@ int hip_fail(hipError_t e, const char* what) {
   return e == hipErrorOutOfMemory ? CAMP_ENOMEM : CAMP_EDEVICE;
 }
 
+// Launch shape and device scratch of a fused wavefront launch with a resolved tuning: 256
+// bytes for the queue counter (int 0) and the cell-order flag (int 16); in launch modes 3
+// and 4 the rate-constant scratch of every resident cell slot; with a caller's cell order,
+// one counter per cell for its permutation check.
+int wave_launch_shape(const DevMech& dm, const Tuning& tu, int n_cells, bool has_order,
+                      WaveShape* out) {
+  if (!wave_lanes_ok(dm.N, 64) || !dm.stage) {
+    set_error("wavefront engine supports at most 576 state variables per cell");
+    return CAMP_EINVAL;
+  }
+  if (!wave_lanes_ok(dm.N, tu.lanes)) {
+    set_error("lanes per cell must be 64, 128 (65..640 state variables) or 256 (129..768)");
+    return CAMP_EINVAL;
+  }
+  WaveShape w;
+  w.lanes = tu.lanes;
+  w.waves = tu.lanes == 64 ? std::max(1, tu.waves) : 1;
+  w.stage = std::max(0, std::min(4, tu.stage));
+  if (wave_wg_lds_bytes(dm, w.waves, w.stage, tu.lanes) > kLdsBytes) {
+    set_error("mechanism does not fit the wavefront engine's LDS budget");
+    return CAMP_EINVAL;
+  }
+  const int wg_total = (n_cells + w.waves - 1) / w.waves;
+  w.persistent = tu.persistent || w.stage >= 3;
+  w.grid = w.persistent ? std::max(1, std::min(wg_total, n_cus() * std::max(1, tu.grid_mult)))
+                        : wg_total;
+  w.kc_bytes = w.stage >= 3 ? sizeof(double) * (size_t)w.grid * w.waves * dm.R : 0;
+  w.seen_bytes = (w.persistent && has_order) ? sizeof(int) * (size_t)n_cells : 0;
+  w.bytes = w.persistent ? 256 + w.kc_bytes + w.seen_bytes : 0;
+  *out = w;
+  return CAMP_OK;
+}
+
+// Enqueues a fused wavefront solve on `stream` using `ws` (at least shape.bytes of device
+// memory, stream-ordered: nothing else may use it until the stream has passed this solve).
+// Launches only kernels: the queue counter and flags are cleared by a fill kernel.
+hipError_t enqueue_wave(const DevMech& dm, const DevEnv& env, double* d_state, int n_cells,
+                        const SolveParams& sp, const int* order, int* d_status,
+                        camp_cell_stats* d_stats, const WaveShape& w, char* ws, bool attr_only,
+                        hipStream_t stream) {
+  if (!w.persistent)
+    return launch_bdf_wave(dm, env, d_state, n_cells, sp, d_status, d_stats, nullptr, nullptr,
+                           w.grid, w.waves, w.stage, w.lanes, attr_only, stream);
+  if (attr_only)
+    return launch_bdf_wave(dm, env, d_state, n_cells, sp, d_status, d_stats, nullptr, nullptr,
+                           w.grid, w.waves, w.stage, w.lanes, true, stream);
+  int* queue = reinterpret_cast<int*>(ws);
+  double* kc = w.stage >= 3 ? reinterpret_cast<double*>(ws + 256) : nullptr;
+  SolveParams spo = sp;
+  hipError_t e = launch_fill_int(queue, 64, 0, stream);
+  if (e == hipSuccess && order) {
+    spo.order = order;
+    spo.order_bad = queue + 16;
+    e = launch_check_order(order, n_cells, reinterpret_cast<int*>(ws + 256 + w.kc_bytes),
+                           queue + 16, stream);
+  }
+  if (e == hipSuccess)
+    e = launch_bdf_wave(dm, env, d_state, n_cells, spo, d_status, d_stats, queue, kc, w.grid,
+                        w.waves, w.stage, w.lanes, false, stream);
+  return e;
+}
+
+// Scratch of fused launches on `stream`, kept per (mechanism, device, stream) and grown when
+// a launch needs more: stream order makes reuse by later solves on the same stream safe.
+int stream_workspace(camp_mech* mh, hipStream_t stream, size_t bytes, char** out) {
+  int device = 0;
+  hipError_t e = hipGetDevice(&device);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  std::lock_guard<std::mutex> g(mh->mu);
+  Workspace& w = mh->ws[std::make_pair(device, (void*)stream)];
+  if (w.bytes < bytes) {
+    if (w.ptr) {
+      e = hipStreamSynchronize(stream);   // earlier solves on this stream may still use it
+      if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize(workspace)");
+      hipFree(w.ptr);
+      w.ptr = nullptr;
+      w.bytes = 0;
+    }
+    const size_t want = std::max(bytes, (size_t)1 << 20);
+    e = hipMalloc((void**)&w.ptr, want);
+    if (e != hipSuccess) return hip_fail(e, "hipMalloc(solve workspace)");
+    w.bytes = want;
+  }
+  *out = w.ptr;
+  return CAMP_OK;
+}
+
 // Dispatch of one device solve with a resolved tuning.
 int solve_device_tuned(camp_mech* mh, const DevMech& dm, int n_cells, double* d_state,
                        const camp_env* d_env, const SolveParams& sp, const camp_opts* opts,
                        int* d_status, camp_cell_stats* d_stats, hipStream_t stream, const Tuning& tu) {
-  (void)mh;
   DevEnv env = make_env(d_env);
   const int use_graph = opts ? opts->use_graph : 0;
   hipError_t e = hipSuccess;
@@ -257,51 +360,16 @@ int solve_device_tuned(camp_mech* mh, const DevMech& dm, int n_cells, double* d_
     const int slots = std::max(256, n_cus() * 4 * 64 * 2);
     e = run_fused_lane(dm, env, d_state, n_cells, sp, d_status, d_stats, slots, stream);
   } else {
-    if (!wave_lanes_ok(dm.N, 64) || !dm.stage) {
-      set_error("wavefront engine supports at most 576 state variables per cell");
-      return CAMP_EINVAL;
+    const int* order = opts ? opts->cell_order : nullptr;
+    WaveShape w;
+    int rc = wave_launch_shape(dm, tu, n_cells, order != nullptr, &w);
+    if (rc != CAMP_OK) return rc;
+    char* ws = nullptr;
+    if (w.bytes) {
+      rc = stream_workspace(mh, stream, w.bytes, &ws);
+      if (rc != CAMP_OK) return rc;
     }
-    if (!wave_lanes_ok(dm.N, tu.lanes)) {
-      set_error("lanes per cell must be 64, 128 (65..640 state variables) or 256 (129..768)");
-      return CAMP_EINVAL;
-    }
-    const int waves = tu.lanes == 64 ? std::max(1, tu.waves) : 1;
-    const int stage = std::max(0, std::min(4, tu.stage));
-    if (wave_wg_lds_bytes(dm, waves, stage, tu.lanes) > kLdsBytes) {
-      set_error("mechanism does not fit the wavefront engine's LDS budget");
-      return CAMP_EINVAL;
-    }
-    const int wg_total = (n_cells + waves - 1) / waves;
-    if (tu.persistent || stage >= 3) {
-      // 256 bytes: queue counter (int 0) and cell-order flag (int 16); then (modes 3, 4) the
-      // rate-constant scratch of every resident wavefront; then, with a cell order, one
-      // counter per cell for its permutation check
-      const int grid = std::max(1, std::min(wg_total, n_cus() * std::max(1, tu.grid_mult)));
-      const size_t kc_bytes = stage >= 3 ? sizeof(double) * (size_t)grid * waves * dm.R : 0;
-      const int* order = opts ? opts->cell_order : nullptr;
-      const size_t seen_bytes = order ? sizeof(int) * (size_t)n_cells : 0;
-      char* buf = nullptr;
-      e = hipMallocAsync((void**)&buf, 256 + kc_bytes + seen_bytes, stream);
-      if (e != hipSuccess) return hip_fail(e, "hipMallocAsync(queue)");
-      int* queue = reinterpret_cast<int*>(buf);
-      double* kc = stage >= 3 ? reinterpret_cast<double*>(buf + 256) : nullptr;
-      SolveParams spo = sp;
-      e = launch_fill_int(queue, 64, 0, stream);
-      if (e == hipSuccess && order) {
-        spo.order = order;
-        spo.order_bad = queue + 16;
-        e = launch_check_order(order, n_cells, reinterpret_cast<int*>(buf + 256 + kc_bytes),
-                               queue + 16, stream);
-      }
-      if (e == hipSuccess)
-        e = launch_bdf_wave(dm, env, d_state, n_cells, spo, d_status, d_stats, queue, kc, grid,
-                            waves, stage, tu.lanes, stream);
-      hipError_t e2 = hipFreeAsync(buf, stream);
-      if (e == hipSuccess) e = e2;
-    } else {
-      e = launch_bdf_wave(dm, env, d_state, n_cells, sp, d_status, d_stats, nullptr, nullptr,
-                          wg_total, waves, stage, tu.lanes, stream);
-    }
+    e = enqueue_wave(dm, env, d_state, n_cells, sp, order, d_status, d_stats, w, ws, false, stream);
   }
   if (e != hipSuccess) return hip_fail(e, "solve launch");
   return CAMP_OK;
@@ -348,6 +416,43 @@ int autotuned(camp_mech* mh, const DevMech& dm, int n_cells, double* d_state,
               const camp_env* d_env, const SolveParams& sp, const camp_opts* opts,
               hipStream_t stream, Tuning* out);
 
+// The launch choice of a device solve: the autotuner's for engine AUTO (run_trials = false:
+// its cached choice for this size bucket, else the occupancy default, never a trial), else
+// the occupancy default for the requested engine with the caller's overrides.
+int resolve_tuning(camp_mech* mh, const DevMech& dm, int n_cells, double* d_state,
+                   const camp_env* d_env, const SolveParams& sp, const camp_opts* opts,
+                   hipStream_t stream, bool run_trials, Tuning* out) {
+  Tuning tu;
+  const int engine = opts ? opts->engine : CAMP_ENGINE_AUTO;
+  if (engine == CAMP_ENGINE_AUTO) {
+    if (run_trials) {
+      int rc = autotuned(mh, dm, n_cells, d_state, d_env, sp, opts, stream, &tu);
+      if (rc != CAMP_OK) return rc;
+    } else if (!cached_tuning(mh, dm, n_cells, sp, &tu)) {
+      tu = default_tuning(dm, n_cells);
+    }
+  } else {
+    tu = default_tuning(dm, n_cells);
+    tu.engine = engine;
+  }
+  if (opts && engine != CAMP_ENGINE_AUTO) {
+    if (opts->persistent >= 0) tu.persistent = opts->persistent ? 1 : 0;
+    if (opts->wg_per_cu > 0) tu.grid_mult = opts->wg_per_cu;
+    if (opts->waves_per_wg > 0) tu.waves = std::min(opts->waves_per_wg, 12);
+    if (opts->lanes_per_cell > 0) tu.lanes = opts->lanes_per_cell;
+    if (opts->stage_tables >= 0) tu.stage = std::min(opts->stage_tables, 4);
+    if (opts->waves_per_wg <= 0 && tu.engine == CAMP_ENGINE_FUSED_WAVE && tu.lanes == 64 &&
+        tu.stage >= 0) {
+      // cells per workgroup not given: the most that this launch mode allows and LDS holds
+      int w = std::min(tu.waves, wave_max_waves(dm.N, tu.stage, 64));
+      while (w > 1 && wave_wg_lds_bytes(dm, w, tu.stage, 64) > kLdsBytes) --w;
+      tu.waves = std::max(1, w);
+    }
+  }
+  *out = tu;
+  return CAMP_OK;
+}
+
 }  // namespace camp
 
 using namespace camp;
@@ -369,7 +474,8 @@ int camp_mech_load(const camp_reaction* rxns, int n_rxn, const camp_species* spe
       set_error(err);
       return CAMP_EINVAL;
     }
-    for (int v = 0; v < 3; ++v) mh->stage[v] = build_stage_block(mh->C, 1 << v);
+    for (int v = 0; v < 3; ++v) mh->stage[v] = build_stage_block(mh->C, 1 << v, true);
+    mh->stage[3] = build_stage_block(mh->C, 1, false);
   } catch (const std::bad_alloc&) {
     delete mh;
     set_error("out of host memory");
@@ -396,6 +502,7 @@ int camp_mech_info(const camp_mech* mh, camp_mech_info_t* info) {
   info->n_partials = C.n_partials;
   info->n_terms = (int)C.term_rxn.size();
   info->n_jac_contrib = (int)C.jc_part.size();
+  info->tail_k = C.tail_k;
   return CAMP_OK;
 }
 
@@ -410,16 +517,54 @@ int camp_mech_export(const camp_mech* mh, int* perm, int* row_ptr, int* col, int
   return CAMP_OK;
 }
 
+int camp_mech_layout_info(const camp_mech* mh, int lanes_per_cell, int* tail_k, int* fwd_levels,
+                          int* bwd_levels, int* lu_levels, int* staged_bytes) {
+  if (!mh) { set_error("NULL mechanism"); return CAMP_EINVAL; }
+  const int v = lanes_per_cell == 64 ? 0 : lanes_per_cell == 128 ? 1 : lanes_per_cell == 256 ? 2 : -1;
+  if (v < 0) { set_error("lanes_per_cell must be 64, 128 or 256"); return CAMP_EINVAL; }
+  const StageBlock& sb = mh->stage[v];
+  if (!sb.ok) { set_error("mechanism exceeds the wavefront engine's table ranges"); return CAMP_EINVAL; }
+  if (tail_k) *tail_k = sb.tail_k;
+  if (fwd_levels) *fwd_levels = sb.n_sf_lev;
+  if (bwd_levels) *bwd_levels = sb.n_sb_lev;
+  if (lu_levels) *lu_levels = sb.n_lu_lev;
+  if (staged_bytes) *staged_bytes = (int)sb.bytes.size();
+  return CAMP_OK;
+}
+
+int camp_emulate_factor_solve(const camp_mech* mh, int lanes_per_cell, int dense_tail, double* m,
+                              double* x) {
+  if (!mh || !m || !x) { set_error("NULL argument"); return CAMP_EINVAL; }
+  const int v = lanes_per_cell == 64 ? (dense_tail ? 0 : 3)
+                : lanes_per_cell == 128 ? 1 : lanes_per_cell == 256 ? 2 : -1;
+  if (v < 0 || (!dense_tail && v != 3)) {
+    set_error("lanes_per_cell must be 64, 128 or 256 (64 only without the dense tail)");
+    return CAMP_EINVAL;
+  }
+  const StageBlock& sb = mh->stage[v];
+  if (!sb.ok) { set_error("mechanism exceeds the wavefront engine's table ranges"); return CAMP_EINVAL; }
+  if (!emulate_factor_solve(mh->C, sb, m, x)) {
+    set_error("zero or non-finite pivot");
+    return CAMP_ESOLVE;
+  }
+  return CAMP_OK;
+}
+
 void camp_mech_free(camp_mech* mh) {
   if (!mh) return;
+  int cur = 0;
+  hipGetDevice(&cur);
   for (auto& kv : mh->dev) {
-    int cur = 0;
-    hipGetDevice(&cur);
     hipSetDevice(kv.first);
     hipDeviceSynchronize();
     hipFree(kv.second.blob);
-    hipSetDevice(cur);
   }
+  for (auto& kv : mh->ws) {
+    hipSetDevice(kv.first.first);
+    hipDeviceSynchronize();
+    hipFree(kv.second.ptr);
+  }
+  hipSetDevice(cur);
   delete mh;
 }
 
@@ -435,31 +580,103 @@ int camp_solve_device(camp_mech* mh, int n_cells, double* d_state, const camp_en
   if (rc != CAMP_OK) return rc;
   const SolveParams sp = make_params(dt, rtol, atol, opts);
   Tuning tu;
-  const int engine = opts ? opts->engine : CAMP_ENGINE_AUTO;
-  if (engine == CAMP_ENGINE_AUTO) {
-    rc = autotuned(mh, *dm, n_cells, d_state, d_env, sp, opts, (hipStream_t)stream, &tu);
-    if (rc != CAMP_OK) return rc;
-  } else {
-    tu = default_tuning(*dm, n_cells);
-    tu.engine = engine;
-  }
-  if (opts && engine != CAMP_ENGINE_AUTO) {
-    if (opts->persistent >= 0) tu.persistent = opts->persistent ? 1 : 0;
-    if (opts->wg_per_cu > 0) tu.grid_mult = opts->wg_per_cu;
-    if (opts->waves_per_wg > 0) tu.waves = std::min(opts->waves_per_wg, 12);
-    if (opts->lanes_per_cell > 0) tu.lanes = opts->lanes_per_cell;
-    if (opts->stage_tables >= 0) tu.stage = std::min(opts->stage_tables, 4);
-    if (opts->waves_per_wg <= 0 && tu.engine == CAMP_ENGINE_FUSED_WAVE && tu.lanes == 64 &&
-        tu.stage >= 0) {
-      // cells per workgroup not given: the most that this launch mode allows and LDS holds
-      int w = std::min(tu.waves, wave_max_waves(dm->N, tu.stage, 64));
-      while (w > 1 && wave_wg_lds_bytes(*dm, w, tu.stage, 64) > kLdsBytes) --w;
-      tu.waves = std::max(1, w);
-    }
-  }
+  rc = resolve_tuning(mh, *dm, n_cells, d_state, d_env, sp, opts, (hipStream_t)stream, true, &tu);
+  if (rc != CAMP_OK) return rc;
   return solve_device_tuned(mh, *dm, n_cells, d_state, d_env, sp, opts, d_status, d_stats,
                             (hipStream_t)stream, tu);
 }
+
+// ---------------------------------------------------------------- plans (captured graphs)
+}  // extern "C"
+
+struct camp_plan {
+  camp_mech* mh = nullptr;
+  int device = 0;
+  char* ws = nullptr;
+  hipStream_t cap = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+namespace {
+void plan_release(camp_plan* p) {
+  if (!p) return;
+  int cur = 0;
+  hipGetDevice(&cur);
+  hipSetDevice(p->device);
+  hipDeviceSynchronize();   // replays on any stream may still use the workspace
+  if (p->exec) hipGraphExecDestroy(p->exec);
+  if (p->graph) hipGraphDestroy(p->graph);
+  if (p->cap) hipStreamDestroy(p->cap);
+  if (p->ws) hipFree(p->ws);
+  hipSetDevice(cur);
+  delete p;
+}
+}  // namespace
+
+extern "C" {
+
+int camp_plan_create(camp_mech* mh, int n_cells, double* d_state, const camp_env* d_env, double dt,
+                     double rtol, double atol, const camp_opts* opts, int* d_status,
+                     camp_cell_stats* d_stats, void* stream, camp_plan** out) {
+  if (!out) { set_error("out is NULL"); return CAMP_EINVAL; }
+  *out = nullptr;
+  int rc = check_solve_args(mh, n_cells, d_state, d_env, dt, rtol, atol);
+  if (rc != CAMP_OK) return rc;
+  if (n_cells < 1 || !d_status) { set_error("a plan needs n_cells >= 1 and d_cell_status"); return CAMP_EINVAL; }
+  const DevMech* dm = nullptr;
+  rc = resident(mh, &dm);
+  if (rc != CAMP_OK) return rc;
+  const SolveParams sp = make_params(dt, rtol, atol, opts);
+  Tuning tu;
+  rc = resolve_tuning(mh, *dm, n_cells, d_state, d_env, sp, opts, (hipStream_t)stream, true, &tu);
+  if (rc != CAMP_OK) return rc;
+  if (tu.engine != CAMP_ENGINE_FUSED_WAVE) {
+    set_error("plans run the fused wavefront engine (engine AUTO or FUSED_WAVE)");
+    return CAMP_EINVAL;
+  }
+  const int* order = opts ? opts->cell_order : nullptr;
+  WaveShape w;
+  rc = wave_launch_shape(*dm, tu, n_cells, order != nullptr, &w);
+  if (rc != CAMP_OK) return rc;
+  camp_plan* p = new (std::nothrow) camp_plan();
+  if (!p) { set_error("out of host memory"); return CAMP_ENOMEM; }
+  p->mh = mh;
+  hipGetDevice(&p->device);
+  const DevEnv env = make_env(d_env);
+  hipError_t e = hipSuccess;
+  if (w.bytes) e = hipMalloc((void**)&p->ws, w.bytes);
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&p->cap, hipStreamNonBlocking);
+  // launch attributes are host state: set them before the capture
+  if (e == hipSuccess)
+    e = enqueue_wave(*dm, env, d_state, n_cells, sp, order, d_status, d_stats, w, p->ws, true, p->cap);
+  if (e == hipSuccess) e = hipStreamBeginCapture(p->cap, hipStreamCaptureModeThreadLocal);
+  if (e == hipSuccess) {
+    hipError_t el = enqueue_wave(*dm, env, d_state, n_cells, sp, order, d_status, d_stats, w,
+                                 p->ws, false, p->cap);
+    e = hipStreamEndCapture(p->cap, &p->graph);
+    if (el != hipSuccess) e = el;
+  }
+  if (e == hipSuccess) e = hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    rc = hip_fail(e, "plan capture");
+    plan_release(p);
+    return rc;
+  }
+  *out = p;
+  return CAMP_OK;
+}
+
+int camp_plan_launch(camp_plan* p, void* stream) {
+  if (!p || !p->exec) { set_error("invalid plan"); return CAMP_EINVAL; }
+  int device = 0;
+  hipGetDevice(&device);
+  if (device != p->device) { set_error("plan belongs to another device"); return CAMP_EINVAL; }
+  hipError_t e = hipGraphLaunch(p->exec, (hipStream_t)stream);
+  return e == hipSuccess ? CAMP_OK : hip_fail(e, "hipGraphLaunch");
+}
+
+void camp_plan_free(camp_plan* p) { plan_release(p); }
 
 int camp_solve(camp_mech* mh, int n_cells, double* state, const camp_env* env, double dt, double rtol,
                double atol, const camp_opts* opts, int* cell_status, camp_cell_stats* cell_stats) {

@@ -152,12 +152,28 @@ std::vector<Tuning> candidates(const DevMech& dm) {
 
 }  // namespace
 
+namespace {
+int size_bucket(int n_cells) { return n_cells <= 1 ? 0 : (int)std::ceil(std::log2((double)n_cells)); }
+}  // namespace
+
+bool cached_tuning(camp_mech* mh, const DevMech& dm, int n_cells, const SolveParams& sp,
+                   Tuning* out) {
+  (void)dm;
+  int device = 0;
+  if (hipGetDevice(&device) != hipSuccess) return false;
+  std::lock_guard<std::mutex> g(mh->mu);
+  auto it = mh->tune.find(std::make_pair(device, size_bucket(n_cells) * 2 + sp.full_newton));
+  if (it == mh->tune.end()) return false;
+  *out = it->second;
+  return true;
+}
+
 int autotuned(camp_mech* mh, const DevMech& dm, int n_cells, double* d_state,
               const camp_env* d_env, const SolveParams& sp, const camp_opts* opts,
               hipStream_t stream, Tuning* out) {
   int device = 0;
   hipGetDevice(&device);
-  const int bucket = n_cells <= 1 ? 0 : (int)std::ceil(std::log2((double)n_cells));
+  const int bucket = size_bucket(n_cells);
   const auto key = std::make_pair(device, bucket * 2 + sp.full_newton);
   {
     std::lock_guard<std::mutex> g(mh->mu);

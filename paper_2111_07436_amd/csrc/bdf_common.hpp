@@ -39,6 +39,14 @@ constexpr double kConstraintFactor = 0.25;
 __device__ __forceinline__ double start_value(double v, double rtol, double atol) {
   return (v < 0.0 && -v <= atol + rtol * -v) ? 0.0 : v;
 }
+// The step has collapsed: below the caller's minimum, or so small relative to the time t
+// reached within the call (t >= 0) that t + h would no longer differ from t. There is no
+// other lower bound: the fastest phase-transfer rates exceed 1e11 s^-1, so a cell may
+// legitimately start with steps far below a picosecond.
+__device__ __forceinline__ bool step_collapsed(double h, double t, double h_min) {
+  return h < h_min || h <= 4.0 * __DBL_EPSILON__ * t;
+}
+
 // Attempts per cell: 0 Newton with Jacobian reuse; 1 full Newton; 2 full Newton with the
 // absolute tolerance tightened by kRetryAtolFactor (a cell whose tiny, atol-controlled
 // species undershoot into the constraint over and over integrates at a tolerance at least

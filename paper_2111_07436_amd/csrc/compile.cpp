@@ -23,6 +23,7 @@ namespace camp {
 namespace {
 
 constexpr double kAvogadro = 6.02214076e23;
+constexpr int kWaveLanes = 64;
 
 bool finite(double v) { return std::isfinite(v); }
 
@@ -179,7 +180,90 @@ std::vector<int> choose_order(int n, const std::vector<std::pair<int, int>>& edg
   return best;
 }
 
+// Dependency levels of the wavefront engine's factor and solve when the last K positions
+// form a dense tail handled through the inverse of their Schur complement (see StageBlock):
+// forward levels over the head rows and the tail rows' head columns, backward levels over
+// the head rows, Crout levels where tail entries sum over head pivots only.
+struct TailCost {
+  int fwd = 0, bwd = 0, lu = 0;
+  // as OrderCost::weight, plus one sweep level for the product with the inverse and one LU
+  // level per Gauss-Jordan step (and one to start it)
+  long long weight(int K) const { return 7LL * (fwd + bwd + (K ? 1 : 0)) + lu + (K ? K + 1 : 0); }
+};
+
+TailCost tail_cost(int n, const Bits& F, int K) {
+  const int s = n - K;
+  TailCost c;
+  std::vector<int> lf(n, 0), lb(n, 0);
+  for (int t = 0; t < n; ++t)
+    for (int j = 0; j < t; ++j)
+      if (F.get(t, j) && (t < s || j < s)) lf[t] = std::max(lf[t], lf[j] + 1);
+  for (int t = s - 1; t >= 0; --t)
+    for (int j = t + 1; j < n; ++j)
+      if (F.get(t, j)) lb[t] = std::max(lb[t], lb[j] + 1);
+  std::vector<int> L((size_t)n * n, 0);
+  for (int m = 0; m < n; ++m) {
+    auto entry = [&](int i, int j) {
+      const bool tail = i >= s && j >= s;
+      const int mn = tail ? s : std::min(i, j);
+      int l = 0;
+      bool task = i > j && !tail;
+      for (int k = 0; k < mn; ++k)
+        if (F.get(i, k) && F.get(k, j)) {
+          l = std::max(l, std::max(L[(size_t)i * n + k], L[(size_t)k * n + j]));
+          task = true;
+        }
+      if (i > j && !tail) l = std::max(l, L[(size_t)j * n + j]);
+      L[(size_t)i * n + j] = task ? l + 1 : 0;
+      c.lu = std::max(c.lu, L[(size_t)i * n + j]);
+    };
+    for (int j = m; j < n; ++j)
+      if (F.get(m, j)) entry(m, j);
+    for (int i = m + 1; i < n; ++i)
+      if (F.get(i, m)) entry(i, m);
+  }
+  for (int t = 0; t < n; ++t) {
+    c.fwd = std::max(c.fwd, lf[t]);
+    c.bwd = std::max(c.bwd, lb[t]);
+  }
+  return c;
+}
+
+// Pattern F with its trailing K x K block made dense.
+Bits with_dense_tail(const Bits& F, int n, int K) {
+  Bits G = F;
+  for (int i = n - K; i < n; ++i)
+    for (int j = n - K; j < n; ++j) G.set(i, j);
+  return G;
+}
+
+// Size of the dense tail: the K (0 or 2..k_max) of least TailCost::weight whose dense block
+// adds at most 6 % to the stored entries. Ties keep the smaller block.
+int choose_tail(int n, const Bits& F, long long nnz, int k_max) {
+  int best_k = 0;
+  long long best_w = tail_cost(n, F, 0).weight(0);
+  for (int K = 2; K <= std::min(k_max, n - 1); ++K) {
+    long long have = 0;
+    for (int i = n - K; i < n; ++i)
+      for (int j = n - K; j < n; ++j) have += F.get(i, j);
+    if (((long long)K * K - have) * 100 > 6 * nnz) continue;
+    const long long w = tail_cost(n, with_dense_tail(F, n, K), K).weight(K);
+    if (w < best_w) {
+      best_w = w;
+      best_k = K;
+    }
+  }
+  return best_k;
+}
+
 }  // namespace
+
+int max_tail(int wave_lists) {
+  // whole rows per wavefront: ceil(K / W) rows of K terms within kTailPerLane per lane
+  int k = 0;
+  while ((k + 1 + wave_lists - 1) / wave_lists * (k + 1) <= kWaveLanes * kTailPerLane) ++k;
+  return k;
+}
 
 std::string compile_mechanism(const camp_reaction* rxns, int n_rxn, const camp_species* sp,
                               int n_sp, const camp_phase* ph, int n_ph, Compiled& C) {
@@ -476,7 +560,17 @@ std::string compile_mechanism(const camp_reaction* rxns, int n_rxn, const camp_s
   Bits F0;
   F0.init(N, N);
   for (auto& e : edges) F0.set(C.iperm[e.first], C.iperm[e.second]);
-  const Bits F = symbolic_fill(N, edges, C.perm);
+  Bits F = symbolic_fill(N, edges, C.perm);
+  {
+    long long nnz = 0, n_part = 0;
+    for (int i = 0; i < N; ++i)
+      for (int j = 0; j < N; ++j) nnz += F.get(i, j);
+    for (const X& x : xs) n_part += x.nr;
+    // Gauss-Jordan keeps 4K doubles in the partials / rates scratch of a cell
+    const int scratch_k = (int)(std::max<long long>(n_part, (long long)xs.size()) / 4);
+    C.tail_k = choose_tail(N, F, nnz, std::min(max_tail(4), scratch_k));
+    if (C.tail_k > 0) F = with_dense_tail(F, N, C.tail_k);
+  }
 
   // ---- CSR of the filled pattern ----
   C.row_ptr.assign(N + 1, 0);
@@ -747,11 +841,20 @@ static std::vector<std::vector<std::pair<int, T>>> split_by_wave(
   return out;
 }
 
-StageBlock build_stage_block(const Compiled& C, int wave_lists) {
+StageBlock build_stage_block(const Compiled& C, int wave_lists, bool use_tail) {
   StageBlock sb;
   const int N = C.n_state, Z = C.nnz, R = C.n_rxn;
   if (N >= 1023 || Z > 65535 || (wave_lists != 1 && wave_lists != 2 && wave_lists != 4)) return sb;
   sb.wave_lists = wave_lists;
+  // dense tail of this layout: the last K positions (K <= the pattern's dense block)
+  const int K = use_tail ? std::min(C.tail_k, max_tail(wave_lists)) : 0;
+  const int ts = N - K;
+  sb.tail_k = K;
+  sb.tail_s = ts;
+  std::vector<int> row_of(Z);
+  for (int i = 0; i < N; ++i)
+    for (int q = C.row_ptr[i]; q < C.row_ptr[i + 1]; ++q) row_of[q] = i;
+  auto in_tail = [&](int q) { return row_of[q] >= ts && C.col[q] >= ts; };
   std::vector<uint8_t>& b = sb.bytes;
   auto put = [&](const void* src, size_t n) {
     size_t off = (b.size() + 15) / 16 * 16;
@@ -772,18 +875,42 @@ StageBlock build_stage_block(const Compiled& C, int wave_lists) {
   sb.off_rx = put(rx.data(), 4 * rx.size());
   std::vector<uint16_t> dg(C.diag.begin(), C.diag.end());
   sb.off_diag = put(dg.data(), 2 * dg.size());
-  // triangular solves: the product terms of each level (levels without terms dropped)
-  auto solve_terms = [&](const std::vector<Task>& tasks, const std::vector<int>& lptr,
-                         const std::vector<int>& pa, const std::vector<int>& pb, int& off,
-                         int& off_lp, int& n_lev) {
+  // triangular solves: the product terms of each level (levels without terms dropped). With
+  // a dense tail, tail rows keep only their terms from head columns in the forward sweep
+  // and none in the backward sweep; levels are recomputed from the remaining dependences
+  // (the tasks are stored in a topological order, and without a tail nothing changes).
+  auto solve_terms = [&](const std::vector<Task>& tasks, const std::vector<int>& pa,
+                         const std::vector<int>& pb, bool forward, int& off, int& off_lp,
+                         int& n_lev) {
+    std::vector<int> lv(N, 0);
+    std::vector<std::pair<int, std::vector<int>>> kept;   // (level, pair indices) per task
+    std::vector<int> kdst;
+    for (const Task& x : tasks) {
+      if (!forward && x.dst >= ts) continue;
+      std::vector<int> qs;
+      int l = 0;
+      for (int q = x.pbeg; q < x.pend; ++q) {
+        if (forward && x.dst >= ts && pb[q] >= ts) continue;
+        qs.push_back(q);
+        l = std::max(l, lv[pb[q]]);
+      }
+      if (forward && qs.empty()) continue;
+      lv[x.dst] = l + 1;
+      kept.push_back({l + 1, std::move(qs)});
+      kdst.push_back(x.dst);
+    }
+    std::vector<int> idx(kept.size());
+    std::iota(idx.begin(), idx.end(), 0);
+    std::stable_sort(idx.begin(), idx.end(), [&](int a, int c) { return kept[a].first < kept[c].first; });
     std::vector<uint32_t> t, lp(1, 0);
     n_lev = 0;
-    for (size_t l = 0; l + 1 < lptr.size(); ++l) {
-      std::vector<std::pair<int, int>> lv;
-      for (int i = lptr[l]; i < lptr[l + 1]; ++i)
-        for (int q = tasks[i].pbeg; q < tasks[i].pend; ++q) lv.push_back({tasks[i].dst, q});
-      if (lv.empty()) continue;
-      for (auto& list : split_by_wave(lv, wave_lists)) {
+    for (size_t a = 0; a < idx.size();) {
+      const int level = kept[idx[a]].first;
+      std::vector<std::pair<int, int>> lvl;
+      for (; a < idx.size() && kept[idx[a]].first == level; ++a)
+        for (int q : kept[idx[a]].second) lvl.push_back({kdst[idx[a]], q});
+      if (lvl.empty()) continue;
+      for (auto& list : split_by_wave(lvl, wave_lists)) {
         for (auto& e : list) {
           t.push_back((uint32_t)e.first | ((uint32_t)pb[e.second] << 16));
           t.push_back((uint32_t)pa[e.second]);
@@ -795,22 +922,49 @@ StageBlock build_stage_block(const Compiled& C, int wave_lists) {
     off = put(t.data(), 4 * t.size());
     off_lp = put(lp.data(), 4 * lp.size());
   };
-  solve_terms(C.fwd_tasks, C.fwd_level_ptr, C.fwd_pa, C.fwd_pb, sb.off_sf, sb.off_sf_lp, sb.n_sf_lev);
-  solve_terms(C.bwd_tasks, C.bwd_level_ptr, C.bwd_pa, C.bwd_pb, sb.off_sb, sb.off_sb_lp, sb.n_sb_lev);
-  // LU: product terms and finalize entries per level
+  solve_terms(C.fwd_tasks, C.fwd_pa, C.fwd_pb, true, sb.off_sf, sb.off_sf_lp, sb.n_sf_lev);
+  solve_terms(C.bwd_tasks, C.bwd_pa, C.bwd_pb, false, sb.off_sb, sb.off_sb_lp, sb.n_sb_lev);
+  // LU: product terms and finalize entries per level. Entries of a dense tail keep only
+  // their products over head pivots and get no finalize entry (they become the Schur
+  // complement, inverted afterwards); levels are recomputed as for the sweeps.
   std::vector<char> is_diag(Z, 0), touched(Z, 0);
   for (int t = 0; t < N; ++t) is_diag[C.diag[t]] = 1;
-  for (const Task& x : C.lu_tasks) touched[x.dst] = 1;
+  struct LuTask {
+    int dst, diag, level;
+    std::vector<int> qs;
+  };
+  std::vector<LuTask> lu;
+  {
+    std::vector<int> lev(Z, 0);
+    for (const Task& x : C.lu_tasks) {
+      const bool tail = in_tail(x.dst);
+      LuTask u{x.dst, tail ? -1 : x.diag, 0, {}};
+      int l = 0;
+      for (int q = x.pbeg; q < x.pend; ++q) {
+        if (tail && C.col[C.lu_pa[q]] >= ts) continue;
+        u.qs.push_back(q);
+        l = std::max(l, std::max(lev[C.lu_pa[q]], lev[C.lu_pb[q]]));
+      }
+      if (u.diag >= 0) l = std::max(l, lev[u.diag]);
+      if (u.qs.empty() && u.diag < 0) continue;   // value final as assembled
+      u.level = l + 1;
+      lev[x.dst] = u.level;
+      touched[x.dst] = 1;
+      lu.push_back(std::move(u));
+    }
+    std::stable_sort(lu.begin(), lu.end(), [](const LuTask& a, const LuTask& c) { return a.level < c.level; });
+  }
   std::vector<uint32_t> lt, ltp(1, 0), lf, lfp(1, 0);
-  for (int t = 0; t < N; ++t)
+  for (int t = 0; t < ts; ++t)
     if (!touched[C.diag[t]]) lf.push_back((uint32_t)C.diag[t] | (0xFFFFu << 16));
   lfp.push_back((uint32_t)lf.size());
-  for (int l = 0; l < C.lu_levels(); ++l) {
+  sb.n_lu_lev = lu.empty() ? 0 : lu.back().level;
+  for (size_t a = 0; a < lu.size();) {
+    const size_t a0 = a;
+    const int level = lu[a].level;
     std::vector<std::pair<int, int>> lv;
-    for (int i = C.lu_level_ptr[l]; i < C.lu_level_ptr[l + 1]; ++i) {
-      const Task& x = C.lu_tasks[i];
-      for (int q = x.pbeg; q < x.pend; ++q) lv.push_back({x.dst, q});
-    }
+    for (; a < lu.size() && lu[a].level == level; ++a)
+      for (int q : lu[a].qs) lv.push_back({lu[a].dst, q});
     for (auto& list : split_by_wave(lv, wave_lists)) {
       for (auto& e : list) {
         lt.push_back((uint32_t)e.first | ((uint32_t)C.lu_pa[e.second] << 16));
@@ -818,26 +972,46 @@ StageBlock build_stage_block(const Compiled& C, int wave_lists) {
       }
       ltp.push_back((uint32_t)(lt.size() / 2));
     }
-    for (int i = C.lu_level_ptr[l]; i < C.lu_level_ptr[l + 1]; ++i) {
-      const Task& x = C.lu_tasks[i];
+    for (size_t i = a0; i < a; ++i) {
+      const LuTask& x = lu[i];
       if (x.diag >= 0)
         lf.push_back((uint32_t)x.dst | ((uint32_t)x.diag << 16));
-      else if (is_diag[x.dst])
+      else if (is_diag[x.dst] && row_of[x.dst] < ts)
         lf.push_back((uint32_t)x.dst | (0xFFFFu << 16));
     }
     lfp.push_back((uint32_t)lf.size());
   }
+  if (lu.empty()) sb.n_lu_lev = 0;
   sb.off_lt = put(lt.data(), 4 * lt.size());
   sb.off_lt_lp = put(ltp.data(), 4 * ltp.size());
   sb.off_lf = put(lf.data(), 4 * lf.size());
   sb.off_lf_lp = put(lfp.data(), 4 * lfp.size());
   // row scaling of the strict upper factor
   std::vector<uint32_t> us;
-  for (int t = 0; t < N; ++t)
+  for (int t = 0; t < ts; ++t)
     for (int q = C.diag[t] + 1; q < C.row_ptr[t + 1]; ++q)
       us.push_back((uint32_t)q | ((uint32_t)C.diag[t] << 16));
   sb.n_us = (int)us.size();
   sb.off_us = put(us.data(), 4 * us.size());
+  // dense tail: the terms of t = S^-1 x[s..N), whole rows per wavefront list
+  {
+    std::vector<std::pair<int, uint32_t>> tt;
+    for (int i = 0; i < K; ++i) {
+      const int r = ts + i;
+      const int q0 = C.row_ptr[r + 1] - K;   // the row's last K entries are its tail columns
+      if (q0 < C.row_ptr[r] || C.col[q0] != ts) return StageBlock{};
+      for (int j = 0; j < K; ++j) tt.push_back({i, (uint32_t)(q0 + j) | ((uint32_t)i << 16) | ((uint32_t)j << 24)});
+    }
+    std::vector<uint32_t> te, tp(1, 0);
+    for (auto& list : split_by_wave(tt, wave_lists)) {
+      if ((int)list.size() > kWaveLanes * kTailPerLane) return StageBlock{};
+      for (auto& e : list) te.push_back(e.second);
+      tp.push_back((uint32_t)te.size());
+    }
+    sb.n_tail = (int)te.size();
+    sb.off_tail = put(te.data(), 4 * te.size());
+    sb.off_tail_lp = put(tp.data(), 4 * tp.size());
+  }
   b.resize((b.size() + 15) / 16 * 16);
   sb.core_bytes = (int)b.size();
   // extension: forcing terms and Jacobian contributions as flat term lists
@@ -874,6 +1048,87 @@ StageBlock build_stage_block(const Compiled& C, int wave_lists) {
   b.resize((b.size() + 15) / 16 * 16);
   sb.ok = true;
   return sb;
+}
+
+}  // namespace camp
+
+namespace camp {
+
+bool emulate_factor_solve(const Compiled& C, const StageBlock& sb, double* M, double* x) {
+  const int N = C.n_state, W = sb.wave_lists, K = sb.tail_k, ts = sb.tail_s;
+  auto u32 = [&](int off, int i) {
+    uint32_t v;
+    std::memcpy(&v, sb.bytes.data() + off + 4 * (size_t)i, 4);
+    return v;
+  };
+  bool ok = true;
+  auto inv = [&](double& v) {
+    if (!(std::fabs(v) > 0.0) || !std::isfinite(v)) ok = false;
+    v = 1.0 / v;
+  };
+  auto finalize = [&](int lo, int hi) {
+    for (int i = lo; i < hi; ++i) {
+      const uint32_t e = u32(sb.off_lf, i);
+      const int dst = e & 0xFFFF, pv = e >> 16;
+      if (pv == 0xFFFF) inv(M[dst]);
+      else M[dst] *= M[pv];
+    }
+  };
+  // factorization levels
+  finalize((int)u32(sb.off_lf_lp, 0), (int)u32(sb.off_lf_lp, 1));
+  for (int l = 0; l < sb.n_lu_lev; ++l) {
+    for (int i = (int)u32(sb.off_lt_lp, W * l); i < (int)u32(sb.off_lt_lp, W * l + W); ++i) {
+      const uint32_t a = u32(sb.off_lt, 2 * i), c = u32(sb.off_lt, 2 * i + 1);
+      M[a & 0xFFFF] -= M[a >> 16] * M[c];
+    }
+    finalize((int)u32(sb.off_lf_lp, l + 1), (int)u32(sb.off_lf_lp, l + 2));
+  }
+  for (int i = 0; i < sb.n_us; ++i) {
+    const uint32_t e = u32(sb.off_us, i);
+    M[e & 0xFFFF] *= M[e >> 16];
+  }
+  // Gauss-Jordan inversion of the tail block in place
+  std::vector<int> slot((size_t)K * K);
+  for (int i = 0; i < sb.n_tail; ++i) {
+    const uint32_t e = u32(sb.off_tail, i);
+    slot[(size_t)((e >> 16) & 0xFF) * K + (e >> 24)] = (int)(e & 0xFFFF);
+  }
+  for (int p = 0; p < K; ++p) {
+    const double piv = M[slot[(size_t)p * K + p]];
+    if (!(std::fabs(piv) > 0.0) || !std::isfinite(piv)) ok = false;
+    const double r = 1.0 / piv;
+    std::vector<double> row(K), col(K);
+    for (int j = 0; j < K; ++j) row[j] = M[slot[(size_t)p * K + j]];
+    for (int i = 0; i < K; ++i) col[i] = M[slot[(size_t)i * K + p]];
+    for (int i = 0; i < K; ++i)
+      for (int j = 0; j < K; ++j) {
+        double& a = M[slot[(size_t)i * K + j]];
+        if (i == p) a = j == p ? r : row[j] * r;
+        else if (j == p) a = -col[i] * r;
+        else a = a - col[i] * row[j] * r;
+      }
+  }
+  for (int t = 0; t < ts; ++t)
+    if (!(std::fabs(M[C.diag[t]]) > 0.0) || !std::isfinite(M[C.diag[t]])) ok = false;
+  // solve
+  auto sweep = [&](int off, int off_lp, int n_lev) {
+    for (int l = 0; l < n_lev; ++l)
+      for (int i = (int)u32(off_lp, W * l); i < (int)u32(off_lp, W * l + W); ++i) {
+        const uint32_t a = u32(off, 2 * i), c = u32(off, 2 * i + 1);
+        x[a & 0xFFFF] -= M[c] * x[a >> 16];
+      }
+  };
+  sweep(sb.off_sf, sb.off_sf_lp, sb.n_sf_lev);
+  std::vector<double> t(K, 0.0);
+  for (int i = 0; i < sb.n_tail; ++i) {
+    const uint32_t e = u32(sb.off_tail, i);
+    t[(e >> 16) & 0xFF] += M[e & 0xFFFF] * x[ts + (e >> 24)];
+  }
+  for (int r = 0; r < ts; ++r) x[r] *= M[C.diag[r]];
+  for (int i = 0; i < K; ++i) x[ts + i] = t[i];
+  sweep(sb.off_sb, sb.off_sb_lp, sb.n_sb_lev);
+  (void)N;
+  return ok;
 }
 
 }  // namespace camp

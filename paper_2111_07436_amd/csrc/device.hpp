@@ -25,6 +25,8 @@ struct StageView {
   int n_sf_lev, n_sb_lev, n_us;
   int so_ft, so_ft_coef, so_jt, so_jt_coef, n_ft, n_jt, so_ft_lp, so_jt_lp;
   int wave_lists;   // per-wavefront term lists per level (1, 2 or 4)
+  int n_lu_lev;     // factorization levels of this layout
+  int tail_k, tail_s, so_tail, so_tail_lp, n_tail;   // dense tail (tail_k = 0: none)
 };
 
 // Device copies of the compiled tables; passed to kernels by value.
@@ -59,8 +61,9 @@ struct DevMech {
   const int2* fwd_pair;
   const int2* bwd_pair;
   // compact tables of the wavefront engine (see StageBlock), one layout per group size:
-  // sv[0] one wavefront per cell, sv[1] two, sv[2] four wavefronts (a workgroup) per cell
-  StageView sv[3];
+  // sv[0] one wavefront per cell, sv[1] two, sv[2] four wavefronts (a workgroup) per cell;
+  // sv[3] one wavefront without the dense tail (single-step kernels)
+  StageView sv[4];
   const uint8_t* stage;   // sv[0].base, null when the mechanism exceeds the 16-bit layout
 };
 

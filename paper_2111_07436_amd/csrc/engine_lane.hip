@@ -299,7 +299,7 @@ __device__ void lane_predict(const LaneCtx& C, int slot, int new_step) {
     }
   }
   const int att = ++S.attempts[slot];
-  if (att > C.sp.max_steps || h < C.sp.h_min) {
+  if (att > C.sp.max_steps || step_collapsed(h, t, C.sp.h_min)) {
     S.phase[slot] = PH_DONE;
     C.status[cell] = att > C.sp.max_steps ? ST_MAX_STEPS : ST_H_MIN;
     return;

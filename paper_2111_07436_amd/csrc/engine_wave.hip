@@ -40,15 +40,16 @@ size_t wave_wg_lds_bytes(const DevMech& m, int waves, int mode, int lanes) {
 hipError_t launch_bdf_wave(const DevMech& m, const DevEnv& env, double* state, int n_cells,
                            const SolveParams& sp, int* status, camp_cell_stats* stats, int* queue,
                            double* kc_glob, int grid, int waves, int stage, int lanes,
-                           hipStream_t stream) {
+                           bool attr_only, hipStream_t stream) {
   if (!wave_lanes_ok(m.N, lanes)) return hipErrorInvalidValue;
   if (stage < 0 || stage > 4) return hipErrorInvalidValue;
   const StageView& view = m.sv[lanes / 128];
   if (!view.base || view.wave_lists != lanes / kWave) return hipErrorInvalidValue;
   if (waves < 1 || waves > wave_max_waves(m.N, stage, lanes)) return hipErrorInvalidValue;
-  if (kc_global(stage) && (!queue || !kc_glob)) return hipErrorInvalidValue;
-  const WaveParams p{m, env, state, n_cells, sp, status, stats, queue, kc_glob, grid, waves,
-                     wave_wg_lds_bytes(m, waves, stage, lanes), stream};
+  if (!attr_only && kc_global(stage) && (!queue || !kc_glob)) return hipErrorInvalidValue;
+  const WaveParams p{m,     env,   state, n_cells, sp,
+                     status, stats, queue, kc_glob, grid,
+                     waves, wave_wg_lds_bytes(m, waves, stage, lanes), attr_only, stream};
   const int npl = (m.N + lanes - 1) / lanes;
   if (lanes == 128) return wave_run_128(p, npl, stage);
   if (lanes == 256) return wave_run_256(p, npl, stage);
@@ -69,11 +70,11 @@ __global__ __launch_bounds__(kWave) void wave_step_kernel(DevMech m, int op, int
                                                           double* out, double gamma) {
   extern __shared__ double lds[];
   const int np = m.n_part > m.R ? m.n_part : m.R;
-  const char* g = reinterpret_cast<const char*>(m.sv[0].base);
+  const char* g = reinterpret_cast<const char*>(m.sv[3].base);
   double* yl = lds + m.Z;
   double* xl = yl + m.N;
   double* P = xl + m.N;
-  const WaveCell<NPL, kWave> W{m, Tabs{g, g, m.sv[0]}, lds, yl, xl, P, P + np + 8, P + np,
+  const WaveCell<NPL, kWave> W{m, Tabs{g, g, m.sv[3]}, lds, yl, xl, P, P + np + 8, P + np,
                                (int)threadIdx.x};
   const int cell = blockIdx.x;
   if (cell >= n_cells) return;

@@ -22,6 +22,7 @@
 
 #include "bdf_common.hpp"
 #include "camp.h"
+#include "mech.hpp"
 
 namespace camp {
 
@@ -38,6 +39,7 @@ struct WaveParams {
   double* kc_glob;
   int grid, waves;
   size_t lds;
+  bool attr_only;   // set the launch attributes only
   hipStream_t stream;
 };
 
@@ -248,6 +250,8 @@ struct Tabs {
   __device__ uint32_t lf(int i) const { return reinterpret_cast<const uint32_t*>(b + v.so_lf)[i]; }
   __device__ int lf_lp(int l) const { return (int)reinterpret_cast<const uint32_t*>(b + v.so_lf_lp)[l]; }
   __device__ uint32_t us(int i) const { return reinterpret_cast<const uint32_t*>(b + v.so_us)[i]; }
+  __device__ uint32_t tl(int i) const { return reinterpret_cast<const uint32_t*>(b + v.so_tail)[i]; }
+  __device__ int tl_lp(int a) const { return (int)reinterpret_cast<const uint32_t*>(b + v.so_tail_lp)[a]; }
 };
 
 template <int NPL, int G>
@@ -380,7 +384,7 @@ struct WaveCell {
   // diagonal, reciprocal pivots on it, and U / diag(U) strictly above. Returns 0 if a
   // pivot is not a finite nonzero.
   __device__ __forceinline__ int lu() const {
-    const int L = m.lu_levels;
+    const int L = tb.v.n_lu_lev;
     auto ltp = [&](int k) { return tb.lt_lp(k); };
     const LevelRange tr = load_ranges<kW>(L, wid(), ltp);
     const LevelPtrs fp = load_levels(L + 1, [&](int l) { return tb.lf_lp(l); });
@@ -457,13 +461,65 @@ struct WaveCell {
       const uint32_t e = tb.us(i);
       M[e & 0xFFFF] *= M[e >> 16];
     }
-    int bad = 0;
-    for (int t = lane; t < m.N; t += G) {
+    int bad = tb.v.tail_k ? tail_invert() : 0;
+    for (int t = lane; t < tb.v.tail_s; t += G) {
       const double r = M[tb.dg(t)];
       if (!(fabs(r) > 0.0) || !isfinite(r)) bad = 1;
     }
     sync();
     return !any(bad);
+  }
+
+  // Dense tail: inverts the trailing K x K block in place (it holds the Schur complement S
+  // after the levels) by Gauss-Jordan elimination without pivoting, one group barrier per
+  // step. A lane keeps its tail entries (whole rows per wavefront) in registers; step p
+  // reads row p and column p of the current matrix from a copy in LDS (P: two sets of a row
+  // and a column, alternating), and the lanes that write the new row and column p + 1 also
+  // write the other set. Returns nonzero if a pivot is zero or not finite.
+  __device__ __forceinline__ int tail_invert() const {
+    const int K = tb.v.tail_k;
+    const int lo = uniform(tb.tl_lp(wid())), hi = uniform(tb.tl_lp(wid() + 1));
+    uint32_t e[kTailPerLane];
+#pragma unroll
+    for (int u = 0; u < kTailPerLane; ++u) {
+      const int i = lo + wlane() + kWave * u;
+      e[u] = i < hi ? tb.tl(i) : 0xFFFFFFFFu;
+    }
+    // row 0 and column 0 of S into set 0
+#pragma unroll
+    for (int u = 0; u < kTailPerLane; ++u) {
+      if (e[u] == 0xFFFFFFFFu) continue;
+      const int i = (e[u] >> 16) & 0xFF, j = e[u] >> 24;
+      const double v = M[e[u] & 0xFFFF];
+      if (i == 0) P[j] = v;
+      if (j == 0) P[K + i] = v;
+    }
+    sync();
+    int bad = 0;
+    for (int p = 0; p < K; ++p) {
+      const double* rp = P + (p & 1) * 2 * K;          // row p
+      const double* cp = rp + K;                       // column p
+      double* rn = P + ((p + 1) & 1) * 2 * K;          // row p + 1 (next set)
+      double* cn = rn + K;                             // column p + 1
+      const double piv = rp[p];
+      if (!(fabs(piv) > 0.0) || !isfinite(piv)) bad = 1;
+      const double r = 1.0 / piv;
+#pragma unroll
+      for (int u = 0; u < kTailPerLane; ++u) {
+        if (e[u] == 0xFFFFFFFFu) continue;
+        const int i = (e[u] >> 16) & 0xFF, j = e[u] >> 24;
+        double* a = &M[e[u] & 0xFFFF];
+        double v;
+        if (i == p) v = j == p ? r : rp[j] * r;
+        else if (j == p) v = -cp[i] * r;
+        else v = *a - cp[i] * rp[j] * r;
+        *a = v;
+        if (j == p + 1) cn[i] = v;
+        if (i == p + 1) rn[j] = v;
+      }
+      sync();
+    }
+    return bad;
   }
 
   __device__ __forceinline__ int newton_matrix_lu(double c) const {
@@ -544,9 +600,24 @@ struct WaveCell {
 
   // xl <- (LU)^-1 xl from the factors lu() leaves: forward sweep, diagonal scaling,
   // backward sweep.
+  // With a dense tail the block's unknowns come from t = S^-1 x[s..N) between the sweeps
+  // (accumulated in P, whole rows per wavefront so each sum has a fixed order).
   __device__ __forceinline__ void solve() const {
+    const int K = tb.v.tail_k, ts = tb.v.tail_s;
+    for (int i = lane; i < K; i += G) P[i] = 0.0;
+    if (K && tb.v.n_sf_lev == 0) sync();
     sweep<true>();
-    for (int t = lane; t < m.N; t += G) xl[t] *= M[tb.dg(t)];
+    if (K) {
+      for_terms<kTermBatch, kWave>(
+          uniform(tb.tl_lp(wid())), uniform(tb.tl_lp(wid() + 1)), wlane(),
+          [&](int i) {
+            const uint32_t e = tb.tl(i);
+            return TermUpdate{(int)((e >> 16) & 0xFF), M[e & 0xFFFF] * xl[ts + (e >> 24)]};
+          },
+          [&](const TermUpdate& u) { lds_add(&P[u.dst], u.v); });
+      sync();
+    }
+    for (int t = lane; t < m.N; t += G) xl[t] = t < ts ? xl[t] * M[tb.dg(t)] : P[t - ts];
     sync();
     sweep<false>();
   }
@@ -665,7 +736,7 @@ __device__ __forceinline__ int integrate(const DevMech& m, double* yrow, const S
     bool accepted = false;
     while (true) {
       if (++attempts > sp.max_steps) { status = ST_MAX_STEPS; break; }
-      if (h < sp.h_min) { status = ST_H_MIN; break; }
+      if (step_collapsed(h, t, sp.h_min)) { status = ST_H_MIN; break; }
       const double gq = bdf_gamma(q);
       const double c = h / gq;
       double psi[NPL], yv[NPL];
@@ -1038,10 +1109,11 @@ __global__ __launch_bounds__((max_threads<NPL, kStage, G>()),
 template <int NPL, int kStage, int G>
 hipError_t launch_wave_npl(const DevMech& m, const DevEnv& env, double* state, int n_cells,
                            const SolveParams& sp, int* status, camp_cell_stats* stats, int* queue,
-                           double* kc_glob, int grid, int waves, size_t lds, hipStream_t stream) {
+                           double* kc_glob, int grid, int waves, size_t lds, bool attr_only,
+                           hipStream_t stream) {
   hipError_t e = hipFuncSetAttribute((const void*)bdf_wave_kernel<NPL, kStage, G>,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  if (e != hipSuccess) return e;
+  if (e != hipSuccess || attr_only) return e;
   const int threads = G == kWave ? kWave * waves : G;
   hipLaunchKernelGGL((bdf_wave_kernel<NPL, kStage, G>), dim3(grid), dim3(threads), lds, stream,
                      m, env, state, n_cells, sp, status, stats, queue, kc_glob);
@@ -1051,11 +1123,11 @@ hipError_t launch_wave_npl(const DevMech& m, const DevEnv& env, double* state, i
 template <int NPL, int G>
 hipError_t run_wave(const WaveParams& p, int stage) {
   switch (stage) {
-    case 0: return launch_wave_npl<NPL, 0, G>(p.m, p.env, p.state, p.n_cells, p.sp, p.status, p.stats, p.queue, p.kc_glob, p.grid, p.waves, p.lds, p.stream);
-    case 1: return launch_wave_npl<NPL, 1, G>(p.m, p.env, p.state, p.n_cells, p.sp, p.status, p.stats, p.queue, p.kc_glob, p.grid, p.waves, p.lds, p.stream);
-    case 2: return launch_wave_npl<NPL, 2, G>(p.m, p.env, p.state, p.n_cells, p.sp, p.status, p.stats, p.queue, p.kc_glob, p.grid, p.waves, p.lds, p.stream);
-    case 3: return launch_wave_npl<NPL, 3, G>(p.m, p.env, p.state, p.n_cells, p.sp, p.status, p.stats, p.queue, p.kc_glob, p.grid, p.waves, p.lds, p.stream);
-    case 4: return launch_wave_npl<NPL, 4, G>(p.m, p.env, p.state, p.n_cells, p.sp, p.status, p.stats, p.queue, p.kc_glob, p.grid, p.waves, p.lds, p.stream);
+    case 0: return launch_wave_npl<NPL, 0, G>(p.m, p.env, p.state, p.n_cells, p.sp, p.status, p.stats, p.queue, p.kc_glob, p.grid, p.waves, p.lds, p.attr_only, p.stream);
+    case 1: return launch_wave_npl<NPL, 1, G>(p.m, p.env, p.state, p.n_cells, p.sp, p.status, p.stats, p.queue, p.kc_glob, p.grid, p.waves, p.lds, p.attr_only, p.stream);
+    case 2: return launch_wave_npl<NPL, 2, G>(p.m, p.env, p.state, p.n_cells, p.sp, p.status, p.stats, p.queue, p.kc_glob, p.grid, p.waves, p.lds, p.attr_only, p.stream);
+    case 3: return launch_wave_npl<NPL, 3, G>(p.m, p.env, p.state, p.n_cells, p.sp, p.status, p.stats, p.queue, p.kc_glob, p.grid, p.waves, p.lds, p.attr_only, p.stream);
+    case 4: return launch_wave_npl<NPL, 4, G>(p.m, p.env, p.state, p.n_cells, p.sp, p.status, p.stats, p.queue, p.kc_glob, p.grid, p.waves, p.lds, p.attr_only, p.stream);
     default: return hipErrorInvalidValue;
   }
 }

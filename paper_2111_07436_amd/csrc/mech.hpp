@@ -53,6 +53,11 @@ struct Compiled {
   int n_state = 0, n_gas = 0, n_inst = 0, n_rxn = 0, n_ext = 0;
   int nnz0 = 0, nnz = 0;
   long long lu_pairs = 0;
+  // Size of the dense trailing block of the filled pattern (0: none). The last tail_k
+  // elimination positions form a fully stored block, so the wavefront engine can replace
+  // their factorization and triangular solves by the explicit inverse of their Schur
+  // complement (see StageBlock).
+  int tail_k = 0;
 
   // phase instance -> phase, first state index (user order)
   std::vector<int> inst_phase, inst_base;
@@ -113,6 +118,18 @@ struct Compiled {
 // workgroup per cell); all terms of one destination are in one list, so the order in
 // which they accumulate is fixed. Pointers u32 [W * levels + 1]: list a of level l spans
 // [ptr[W l + a], ptr[W l + a + 1]).
+// Dense tail (tail_k = K > 0, s = N - K): the trailing K x K block is stored in full. The
+// LU levels then compute, for entries of that block, only the Schur complement
+//   S_ij = M_ij - sum_{k < s} L_ik U_kj
+// (no pivot division, no pivot inversion), and after the levels the block is inverted in
+// place by Gauss-Jordan elimination (K steps), leaving S^-1. Rows below s are factored as
+// usual. A solve is then: forward sweep over the head rows and the tail rows' L entries in
+// head columns; t = S^-1 x[s..N) (the tail terms {slot | i << 16 | j << 24}: t[i] +=
+// M[slot] x[s + j]); head rows scaled by their reciprocal pivots, x[s + i] = t[i]; backward
+// sweep over the head rows. This replaces the tail's chain of one-row sweep levels by one
+// level. The tail terms are stored as W per-wavefront lists, whole rows per list, with
+// pointers u32 [W + 1]; LU levels of the layout: n_lu_lev.
+//
 // The block has a core part (the above) followed by an extension with the forcing terms
 // (u32 {species | reaction << 16}, coef f64) and the Jacobian contributions
 // (u32 {slot | partial << 16}, coef f64), W lists each with pointers u32 [W + 1], so a
@@ -128,12 +145,25 @@ struct StageBlock {
   int off_ft = 0, off_ft_coef = 0, off_jt = 0, off_jt_coef = 0, n_ft = 0, n_jt = 0;
   int off_ft_lp = 0, off_jt_lp = 0;
   int wave_lists = 1;
+  int n_lu_lev = 0;
+  int tail_k = 0, tail_s = 0, off_tail = 0, off_tail_lp = 0, n_tail = 0;
   bool ok = false;   // false when the mechanism exceeds the 16-bit index ranges
 };
 
+// Largest dense tail a layout supports: every wavefront holds at most kTailPerLane tail
+// terms per lane (whole rows per wavefront), and Gauss-Jordan needs 4K doubles of scratch.
+constexpr int kTailPerLane = 8;
+int max_tail(int wave_lists);
+
 // wave_lists: per-wavefront term lists per level, 1 (one wavefront per cell), 2 or 4 (one
-// workgroup of that many wavefronts per cell).
-StageBlock build_stage_block(const Compiled& C, int wave_lists);
+// workgroup of that many wavefronts per cell). use_tail: apply the dense tail (C.tail_k,
+// limited to max_tail(wave_lists)); false builds the plain LU and solve tables.
+StageBlock build_stage_block(const Compiled& C, int wave_lists, bool use_tail);
+
+// Host emulation of a stage block's table program, level by level, for validation:
+// factors m[Z] (a Newton matrix in slot order) in place, then solves the system for
+// x[N] (elimination order) in place. Returns false if a pivot is zero or not finite.
+bool emulate_factor_solve(const Compiled& C, const StageBlock& sb, double* m, double* x);
 
 // Returns an empty string on success, else the validation/compile error.
 std::string compile_mechanism(const camp_reaction* rxns, int n_rxn, const camp_species* sp,
