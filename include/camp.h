@@ -51,7 +51,7 @@ enum {
   CAMP_CELL_NONFINITE = 5     /* non-finite rate constant, forcing or weight       */
 };
 
-/* Process types (paper Sect. 2.2.1, table of Process-extending classes).
+/* Process types (paper Sect. 2.2.1, tables of Process-extending classes).
  * p[] meanings:
  *  ARRHENIUS            gas. k = A exp(-Ea/(kb T)) (T/D)^B (1 + E P).
  *                       p = {A [(molecule cm^-3)^-(n_r-1) s^-1], Ea/kb [K], B, D [K], E [Pa^-1]}.
@@ -70,6 +70,22 @@ enum {
  *  SIMPOL_TRANSFER      as HENRY_TRANSFER; p = {B1, B2, B3, B4}, log10 p0[atm] =
  *                       B1/T + B2 + B3 T + B4 ln T; evaporation k_c p0 101325 / (R T n_abs),
  *                       n_abs = mass / mw_absorber of the instance.
+ *  TROE                 gas fall-off reaction: k = k0[M] / (1 + k0[M]/kinf)
+ *                       Fc^(1 / (1 + (1/N) log10(k0[M]/kinf)^2)), with k0 and kinf of
+ *                       Arrhenius form A exp(-Ea/(kb T)) (T/300)^B and [M] = P / (kb T) the
+ *                       number density of air [molecule cm^-3].
+ *                       p = {A0, Ea0/kb, B0, Ainf, Eainf/kb, Binf, Fc, N}.
+ *  CUSTOM_H2O2          gas: k = k1 + k2[M] (k1, k2 of Arrhenius form as for TROE).
+ *                       p = {A1, Ea1/kb, B1, A2, Ea2/kb, B2}.
+ *  CUSTOM_OH_HNO3       gas: k = k0 + k3[M] / (1 + k3[M]/k2).
+ *                       p = {A0, Ea0/kb, B0, A2, Ea2/kb, B2, A3, Ea3/kb, B3}.
+ *  WENNBERG_TUNNELING   gas: k = A exp(-B/T) exp(C/T^3). p = {A, B [K], C [K^3]}.
+ *                       The gas-phase forms above give k in (molecule cm^-3)^-(n_r-1) s^-1.
+ *  AQUEOUS_REVERSIBLE   reactants <-> products in .phase (every instance), on molarities
+ *                       (phase volume = mass / density): reverse k_r [M^-(n_p-1) s^-1],
+ *                       equilibrium K = A exp(C (1/T - 1/298)) [M^(n_p-n_r)], forward
+ *                       K k_r. Products distinct with yield 1. p = {A, C [K], k_r}. Expands to
+ *                       a forward and a reverse reaction per instance.
  * A phase instance with zero mass has all its rate constants equal to 0.
  */
 enum {
@@ -79,7 +95,12 @@ enum {
   CAMP_RXN_FIRST_ORDER_LOSS = 4,
   CAMP_RXN_CONDENSED_ARRHENIUS = 5,
   CAMP_RXN_HENRY_TRANSFER = 6,
-  CAMP_RXN_SIMPOL_TRANSFER = 7
+  CAMP_RXN_SIMPOL_TRANSFER = 7,
+  CAMP_RXN_TROE = 8,
+  CAMP_RXN_CUSTOM_H2O2 = 9,
+  CAMP_RXN_CUSTOM_OH_HNO3 = 10,
+  CAMP_RXN_WENNBERG_TUNNELING = 11,
+  CAMP_RXN_AQUEOUS_REVERSIBLE = 12
 };
 
 typedef struct {
@@ -107,7 +128,7 @@ typedef struct {
   int n_prod;             /* 0..3, distinct                                          */
   int prod[3];
   double yield[3];        /* molar yields of the products                            */
-  double p[6];            /* type-specific parameters, see above                     */
+  double p[10];           /* type-specific parameters, see above                     */
 } camp_reaction;
 
 typedef struct camp_mech camp_mech;
@@ -139,6 +160,8 @@ typedef struct {
   int n_terms;          /* forcing terms (species x reaction with nonzero net coef)  */
   int n_jac_contrib;    /* Jacobian contributions                                    */
   int tail_k;           /* size of the dense trailing block of the filled pattern        */
+  int nnz_lu;           /* entries of the symbolic LU fill (nnz_fill less the zeros the  */
+                        /* dense trailing block adds)                                    */
 } camp_mech_info_t;
 
 int camp_mech_info(const camp_mech* mech, camp_mech_info_t* info);
@@ -156,6 +179,13 @@ int camp_mech_export(const camp_mech* mech, int* perm, int* row_ptr, int* col, i
  * Any output pointer may be NULL. */
 int camp_mech_layout_info(const camp_mech* mech, int lanes_per_cell, int* tail_k, int* fwd_levels,
                           int* bwd_levels, int* lu_levels, int* staged_bytes);
+
+/* The autotuner's cached launch choice for (mechanism, current device, size bucket of
+ * n_cells): engine, lanes per cell, launch mode (camp_opts.stage_tables), cells per
+ * workgroup and persistent workgroups per CU (0: one workgroup per cell batch). CAMP_EINVAL
+ * if no engine-AUTO solve of that size bucket has run on this device. Outputs may be NULL. */
+int camp_tuned_launch(camp_mech* mech, int n_cells, int* engine, int* lanes_per_cell,
+                      int* launch_mode, int* cells_per_wg, int* wg_per_cu);
 
 /* Validation: runs the fused kernel's factor-and-solve table program on the host, in
  * order, for one matrix (paper Sect. 2.4.1: the sparse direct solve of each Newton

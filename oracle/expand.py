@@ -4,7 +4,9 @@ A Process that acts on an aerosol phase is applied identically to every instance
 phase (Sect. 2.2.3 and Sect. 2.4.2: the Process operates on each instance as determined
 by the aerosol scheme). Gas-phase Processes apply once. Phase transfer
 (HenrysLawPhaseTransfer, SimpolPhaseTransfer) becomes, per instance, a condensation
-reaction G -> A and an evaporation reaction A -> G.
+reaction G -> A and an evaporation reaction A -> G; an AqueousReversible reaction becomes,
+per instance, the forward reaction and the reverse one (products -> reactants, a repeated
+reactant returning as a product of that multiplicity).
 
 State layout: gas species in input order; then for each phase, for each instance, the
 phase's species in the order the phase lists them.
@@ -13,10 +15,13 @@ from dataclasses import dataclass
 from typing import List
 
 ARRHENIUS, PHOTOLYSIS, EMISSION, LOSS, CONDENSED, HENRY, SIMPOL = 1, 2, 3, 4, 5, 6, 7
+TROE, CUSTOM_H2O2, CUSTOM_OH_HNO3, TUNNELING, AQ_REVERSIBLE = 8, 9, 10, 11, 12
 
 # kind of rate constant an expanded reaction carries
 K_ARRHENIUS, K_PHOTOLYSIS, K_EMISSION, K_LOSS, K_CONDENSED = 1, 2, 3, 4, 5
 K_HENRY_COND, K_HENRY_EVAP, K_SIMPOL_COND, K_SIMPOL_EVAP = 6, 7, 8, 9
+K_TROE, K_H2O2, K_OHHNO3, K_TUNNEL, K_AQREV_FWD, K_AQREV_REV = 10, 11, 12, 13, 14, 15
+GAS_SPECIAL = {TROE: K_TROE, CUSTOM_H2O2: K_H2O2, CUSTOM_OH_HNO3: K_OHHNO3, TUNNELING: K_TUNNEL}
 
 
 @dataclass
@@ -74,6 +79,19 @@ def expand(mech) -> Expanded:
                 n_ext += 1
             rxns.append(XReaction(kind, ri, -1, [gas_state[s] for s in r.react],
                                   [gas_state[s] for s in r.prod], list(r.yields), ext))
+        elif t in GAS_SPECIAL:
+            rxns.append(XReaction(GAS_SPECIAL[t], ri, -1, [gas_state[s] for s in r.react],
+                                  [gas_state[s] for s in r.prod], list(r.yields)))
+        elif t == AQ_REVERSIBLE:
+            p = r.phase
+            back = sorted(set(r.react), key=r.react.index)
+            for i in range(mech.phases[p].n_instances):
+                g = first_inst[p] + i
+                rxns.append(XReaction(K_AQREV_FWD, ri, g, [cond_index(p, i, s) for s in r.react],
+                                      [cond_index(p, i, s) for s in r.prod], [1.0] * len(r.prod)))
+                rxns.append(XReaction(K_AQREV_REV, ri, g, [cond_index(p, i, s) for s in r.prod],
+                                      [cond_index(p, i, s) for s in back],
+                                      [float(r.react.count(s)) for s in back]))
         elif t == CONDENSED:
             p = r.phase
             for i in range(mech.phases[p].n_instances):

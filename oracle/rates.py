@@ -25,6 +25,14 @@ State concentrations are mol m^-3 of air. Formulas (Table of Process classes):
   SIMPOL.1: log10 p0[atm] = B1/T + B2 + B3 T + B4 ln T; with Raoult's law over a fixed
   absorbing amount n_abs = m / MW_abs, G_eq = (A / n_abs) p0 101325 / (R T), so
   k_evap = k_c p0 101325 / (R T n_abs).
+* Troe fall-off: k = k0[M] / (1 + k0[M]/kinf) Fc^E with E = 1 / (1 + (1/N) log10(k0[M]/kinf)^2);
+  CustomH2o2: k = k1 + k2[M]; CustomOhHno3: k = k0 + k3[M] / (1 + k3[M]/k2); every k_i of
+  the Arrhenius form with D = 300 K and E = 0, [M] the number density of air (molecule
+  cm^-3, ideal gas). WennbergTunneling: k = A exp(-B/T) exp(C/T^3). All in molecule cm^-3
+  units, converted as the Arrhenius form.
+* AqueousReversible: K_eq = A exp(C (1/T - 1/298)); reverse rate constant k_r, forward
+  K_eq k_r; both act on molarities like an aqueous CondensedPhaseArrhenius rate, so in air
+  units k (1000 V)^(1 - n) with n the reactant count of that direction.
 * An instance with zero phase mass has no particles and no phase volume: every rate
   constant of that instance is 0 (the limit 0 * (1/0) is taken as 0).
 """
@@ -33,9 +41,11 @@ import math
 import numpy as np
 
 from .expand import (K_ARRHENIUS, K_PHOTOLYSIS, K_EMISSION, K_LOSS, K_CONDENSED,
-                     K_HENRY_COND, K_HENRY_EVAP, K_SIMPOL_COND, K_SIMPOL_EVAP)
+                     K_HENRY_COND, K_HENRY_EVAP, K_SIMPOL_COND, K_SIMPOL_EVAP,
+                     K_TROE, K_H2O2, K_OHHNO3, K_TUNNEL, K_AQREV_FWD, K_AQREV_REV)
 
 AVOGADRO = 6.02214076e23          # mol^-1
+BOLTZMANN = 1.380649e-23          # J K^-1
 GAS_CONSTANT = 8.314462618        # J mol^-1 K^-1
 ATM_PA = 101325.0                 # Pa atm^-1
 MOLEC_CM3_PER_MOL_M3 = AVOGADRO * 1.0e-6
@@ -49,6 +59,47 @@ def arrhenius(A, Ea_K, B, D, E, T, P):
     if E != 0.0:
         k *= 1.0 + E * P
     return k
+
+
+def air_number_density(T, P):
+    """[M]: molecules per cm^3 of an ideal gas at T (K), P (Pa)."""
+    return P / (BOLTZMANN * T) * 1.0e-6
+
+
+def arrhenius_300(A, Ea_K, B, T):
+    """The Arrhenius form with D = 300 K and E = 0."""
+    return arrhenius(A, Ea_K, B, 300.0, 0.0, T, 0.0)
+
+
+def troe(p, T, P):
+    """Troe fall-off rate constant; p = [A0, Ea0, B0, Ainf, Eainf, Binf, Fc, N]."""
+    k0m = arrhenius_300(p[0], p[1], p[2], T) * air_number_density(T, P)
+    kinf = arrhenius_300(p[3], p[4], p[5], T)
+    if k0m == 0.0:
+        return 0.0
+    x = math.log10(k0m / kinf)
+    return k0m / (1.0 + k0m / kinf) * p[6] ** (1.0 / (1.0 + x * x / p[7]))
+
+
+def custom_h2o2(p, T, P):
+    """k1 + k2 [M]; p = [A1, Ea1, B1, A2, Ea2, B2]."""
+    return arrhenius_300(p[0], p[1], p[2], T) + arrhenius_300(p[3], p[4], p[5], T) * air_number_density(T, P)
+
+
+def custom_oh_hno3(p, T, P):
+    """k0 + k3[M] / (1 + k3[M]/k2); p = [A0, Ea0, B0, A2, Ea2, B2, A3, Ea3, B3]."""
+    k3m = arrhenius_300(p[6], p[7], p[8], T) * air_number_density(T, P)
+    return arrhenius_300(p[0], p[1], p[2], T) + k3m / (1.0 + k3m / arrhenius_300(p[3], p[4], p[5], T))
+
+
+def tunneling(p, T):
+    """A exp(-B/T) exp(C/T^3)."""
+    return p[0] * math.exp(-p[1] / T) * math.exp(p[2] / T ** 3)
+
+
+def equilibrium_constant(A, C, T):
+    """K_eq(T) = A exp(C (1/T - 1/298))."""
+    return A * math.exp(C * (1.0 / T - 1.0 / 298.0))
 
 
 def fuchs_sutugin(Kn, alpha):
@@ -83,6 +134,10 @@ def rate_constants_cell(mech, x, T, P, cos_sza, radius, mass, override=None):
         if xr.kind == K_ARRHENIUS:
             nr = len(xr.react)
             k[n] = arrhenius(p[0], p[1], p[2], p[3], p[4], T, P) * MOLEC_CM3_PER_MOL_M3 ** (nr - 1)
+        elif xr.kind in (K_TROE, K_H2O2, K_OHHNO3, K_TUNNEL):
+            f = {K_TROE: lambda: troe(p, T, P), K_H2O2: lambda: custom_h2o2(p, T, P),
+                 K_OHHNO3: lambda: custom_oh_hno3(p, T, P), K_TUNNEL: lambda: tunneling(p, T)}
+            k[n] = f[xr.kind]() * MOLEC_CM3_PER_MOL_M3 ** (len(xr.react) - 1)
         elif xr.kind in (K_PHOTOLYSIS, K_EMISSION, K_LOSS):
             if override is not None:
                 k[n] = override[xr.ext]
@@ -99,6 +154,12 @@ def rate_constants_cell(mech, x, T, P, cos_sza, radius, mass, override=None):
                 continue
             rad = radius[g]
             volume = m / ph.density
+            if xr.kind in (K_AQREV_FWD, K_AQREV_REV):
+                kk = p[2]
+                if xr.kind == K_AQREV_FWD:
+                    kk *= equilibrium_constant(p[0], p[1], T)
+                k[n] = kk * (1000.0 * volume) ** (1 - len(xr.react))
+                continue
             if xr.kind == K_CONDENSED:
                 kk = arrhenius(p[0], p[1], p[2], p[3], p[4], T, P)
                 if p[5] != 0.0:

@@ -50,7 +50,7 @@ class Phase(C.Structure):
 class Reaction(C.Structure):
     _fields_ = [("type", C.c_int), ("phase", C.c_int), ("n_react", C.c_int), ("react", C.c_int * 3),
                 ("n_prod", C.c_int), ("prod", C.c_int * 3), ("yield_", C.c_double * 3),
-                ("p", C.c_double * 6)]
+                ("p", C.c_double * 10)]
 
 
 class MechInfo(C.Structure):
@@ -58,7 +58,8 @@ class MechInfo(C.Structure):
                 ("n_rxn_expanded", C.c_int), ("n_external", C.c_int), ("nnz_pattern", C.c_int),
                 ("nnz_fill", C.c_int), ("lu_pairs", C.c_longlong), ("lu_levels", C.c_int),
                 ("fwd_levels", C.c_int), ("bwd_levels", C.c_int), ("n_partials", C.c_int),
-                ("n_terms", C.c_int), ("n_jac_contrib", C.c_int), ("tail_k", C.c_int)]
+                ("n_terms", C.c_int), ("n_jac_contrib", C.c_int), ("tail_k", C.c_int),
+                ("nnz_lu", C.c_int)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -93,6 +94,7 @@ _sig = {
     "camp_mech_free": (None, [_P]),
     "camp_emulate_factor_solve": (C.c_int, [_P, C.c_int, C.c_int, _P, _P]),
     "camp_mech_layout_info": (C.c_int, [_P, C.c_int, _P, _P, _P, _P, _P]),
+    "camp_tuned_launch": (C.c_int, [_P, C.c_int, _P, _P, _P, _P, _P]),
     "camp_solve": (C.c_int, [_P, C.c_int, _P, C.POINTER(Env), C.c_double, C.c_double, C.c_double,
                              C.POINTER(Opts), _P, _P]),
     "camp_solve_device": (C.c_int, [_P, C.c_int, _P, C.POINTER(Env), C.c_double, C.c_double,
@@ -194,7 +196,7 @@ class Mech:
             for k, v in enumerate(r.prod):
                 rr.prod[k] = v
                 rr.yield_[k] = r.yields[k]
-            for k, v in enumerate(list(r.p)[:6]):
+            for k, v in enumerate(list(r.p)[:10]):
                 rr.p[k] = v
             rx[i] = rr
         h = C.c_void_p()
@@ -243,6 +245,14 @@ class Mech:
         v = [C.c_int(0) for _ in range(5)]
         _check(_lib.camp_mech_layout_info(self.h, int(lanes_per_cell), *[C.byref(a) for a in v]))
         return dict(zip(["tail_k", "fwd_levels", "bwd_levels", "lu_levels", "staged_bytes"],
+                        [a.value for a in v]))
+
+    def tuned_launch(self, n_cells):
+        """camp_tuned_launch: the autotuner's cached choice for this size bucket, or None."""
+        v = [C.c_int(0) for _ in range(5)]
+        if _lib.camp_tuned_launch(self.h, int(n_cells), *[C.byref(a) for a in v]) != OK:
+            return None
+        return dict(zip(["engine", "lanes_per_cell", "launch_mode", "cells_per_wg", "wg_per_cu"],
                         [a.value for a in v]))
 
     def emulate_factor_solve(self, m, b, lanes_per_cell=64, dense_tail=True):

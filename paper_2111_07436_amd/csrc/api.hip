@@ -165,6 +165,7 @@ int upload(camp_mech* mh, int device, DeviceTables& out) {
     w.so_tail = sb.off_tail;
     w.so_tail_lp = sb.off_tail_lp;
     w.n_tail = sb.n_tail;
+    w.so_tail_rs = sb.off_tail_rs;
   }
   d.stage = d.sv[0].base;
   out.device = device;
@@ -503,6 +504,7 @@ int camp_mech_info(const camp_mech* mh, camp_mech_info_t* info) {
   info->n_terms = (int)C.term_rxn.size();
   info->n_jac_contrib = (int)C.jc_part.size();
   info->tail_k = C.tail_k;
+  info->nnz_lu = C.nnz_lu;
   return CAMP_OK;
 }
 
@@ -529,6 +531,23 @@ int camp_mech_layout_info(const camp_mech* mh, int lanes_per_cell, int* tail_k, 
   if (bwd_levels) *bwd_levels = sb.n_sb_lev;
   if (lu_levels) *lu_levels = sb.n_lu_lev;
   if (staged_bytes) *staged_bytes = (int)sb.bytes.size();
+  return CAMP_OK;
+}
+
+int camp_tuned_launch(camp_mech* mh, int n_cells, int* engine, int* lanes_per_cell, int* launch_mode,
+                      int* cells_per_wg, int* wg_per_cu) {
+  if (!mh || n_cells < 1) { set_error("bad argument"); return CAMP_EINVAL; }
+  const DevMech* dm = resident_if_uploaded(mh);
+  Tuning tu;
+  if (!dm || !cached_tuning(mh, *dm, n_cells, make_params(1.0, 1e-4, 0.0, nullptr), &tu)) {
+    set_error("no autotuned launch for this mechanism, device and size bucket yet");
+    return CAMP_EINVAL;
+  }
+  if (engine) *engine = tu.engine;
+  if (lanes_per_cell) *lanes_per_cell = tu.lanes;
+  if (launch_mode) *launch_mode = tu.stage;
+  if (cells_per_wg) *cells_per_wg = tu.lanes == 64 ? tu.waves : 1;
+  if (wg_per_cu) *wg_per_cu = tu.persistent ? tu.grid_mult : 0;
   return CAMP_OK;
 }
 

@@ -62,8 +62,11 @@ enum CellStatus : int { ST_OK = 0, ST_MAX_STEPS = 1, ST_H_MIN = 2, ST_ERR_FAIL =
 // P(t_n - m rho h) = sum_k R_k(m) D[k] with R_k(m) = prod_{i=1}^{k} (i-1-m rho)/i, i.e. the
 // Horner form D0 + c_1(m)(D1 + c_2(m)(D2 + ...)) with c_k(m) = (k-1-m rho)/k. Evaluating P
 // at m = 0..q new steps back and differencing those values gives the new D[1..q].
+// (k is a compile-time constant wherever this is called: the division is a multiplication by
+// the reciprocal, exact for k = 1, 2, 4.)
 __device__ __forceinline__ double rescale_coef(int k, int m, double rho) {
-  return ((double)(k - 1) - m * rho) / k;
+  const double inv_k = k == 1 ? 1.0 : k == 2 ? 0.5 : k == 3 ? 1.0 / 3.0 : k == 4 ? 0.25 : 0.2;
+  return ((double)(k - 1) - m * rho) * inv_k;
 }
 
 // Starting step (Hairer, Norsett & Wanner I, Sect. II.4) for order 1.

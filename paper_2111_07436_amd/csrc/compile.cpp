@@ -186,9 +186,11 @@ std::vector<int> choose_order(int n, const std::vector<std::pair<int, int>>& edg
 // the head rows, Crout levels where tail entries sum over head pivots only.
 struct TailCost {
   int fwd = 0, bwd = 0, lu = 0;
-  // as OrderCost::weight, plus one sweep level for the product with the inverse and one LU
-  // level per Gauss-Jordan step (and one to start it)
-  long long weight(int K) const { return 7LL * (fwd + bwd + (K ? 1 : 0)) + lu + (K ? K + 1 : 0); }
+  // Measured on the fused kernel (cycles of one group): a sweep level costs about a third of
+  // an LU level, a Gauss-Jordan step about a quarter, and one LU serves about seven Newton
+  // iterations; weights per iteration: sweep level 7, LU level 3, Gauss-Jordan step 1, plus
+  // one sweep level for the product with the inverse.
+  long long weight(int K) const { return 7LL * (fwd + bwd + (K ? 1 : 0)) + 3LL * lu + (K ? K + 1 : 0); }
 };
 
 TailCost tail_cost(int n, const Bits& F, int K) {
@@ -259,9 +261,14 @@ int choose_tail(int n, const Bits& F, long long nnz, int k_max) {
 }  // namespace
 
 int max_tail(int wave_lists) {
-  // whole rows per wavefront: ceil(K / W) rows of K terms within kTailPerLane per lane
+  // rows per wavefront ceil(K / W), split over max(1, 64 / K) lane groups, at most
+  // kTailPerLane per lane; K <= 64 (one column per lane)
+  auto fits = [&](int K) {
+    const int rows = (K + wave_lists - 1) / wave_lists, groups = std::max(1, kWaveLanes / K);
+    return (rows + groups - 1) / groups <= (wave_lists == 1 ? kTailPerLaneOneWave : kTailPerLane);
+  };
   int k = 0;
-  while ((k + 1 + wave_lists - 1) / wave_lists * (k + 1) <= kWaveLanes * kTailPerLane) ++k;
+  while (k + 1 <= kWaveLanes && fits(k + 1)) ++k;
   return k;
 }
 
@@ -342,7 +349,7 @@ std::string compile_mechanism(const camp_reaction* rxns, int n_rxn, const camp_s
   int n_ext = 0;
   for (int r = 0; r < n_rxn; ++r) {
     const camp_reaction& q = rxns[r];
-    for (int v = 0; v < 6; ++v)
+    for (int v = 0; v < 10; ++v)
       if (!finite(q.p[v])) {
         err << "reaction " << r << " has a non-finite parameter";
         return err.str();
@@ -379,8 +386,10 @@ std::string compile_mechanism(const camp_reaction* rxns, int n_rxn, const camp_s
       s.inst = -1;
       return s;
     };
+    const bool gas_special = t == CAMP_RXN_TROE || t == CAMP_RXN_CUSTOM_H2O2 ||
+                             t == CAMP_RXN_CUSTOM_OH_HNO3 || t == CAMP_RXN_WENNBERG_TUNNELING;
     if (t == CAMP_RXN_ARRHENIUS || t == CAMP_RXN_PHOTOLYSIS || t == CAMP_RXN_EMISSION ||
-        t == CAMP_RXN_FIRST_ORDER_LOSS) {
+        t == CAMP_RXN_FIRST_ORDER_LOSS || gas_special) {
       for (int k = 0; k < q.n_react; ++k)
         if (gas_state[q.react[k]] < 0) {
           err << "reaction " << r << ": gas-phase process with a condensed reactant";
@@ -392,7 +401,27 @@ std::string compile_mechanism(const camp_reaction* rxns, int n_rxn, const camp_s
           return err.str();
         }
       RateSpec s;
-      if (t == CAMP_RXN_ARRHENIUS) {
+      if (gas_special) {
+        // positive pre-exponential factors where the form divides by them; Fc, N > 0
+        bool ok = true;
+        if (t == CAMP_RXN_TROE)
+          ok = q.p[0] >= 0 && q.p[3] > 0 && q.p[6] > 0 && q.p[7] > 0;
+        else if (t == CAMP_RXN_CUSTOM_H2O2)
+          ok = q.p[0] >= 0 && q.p[3] >= 0;
+        else if (t == CAMP_RXN_CUSTOM_OH_HNO3)
+          ok = q.p[0] >= 0 && q.p[3] > 0 && q.p[6] >= 0;
+        else
+          ok = q.p[0] >= 0;
+        if (!ok) {
+          err << "reaction " << r << ": invalid rate parameters for its type";
+          return err.str();
+        }
+        s = base_spec(t == CAMP_RXN_TROE ? KR_TROE
+                      : t == CAMP_RXN_CUSTOM_H2O2 ? KR_H2O2
+                      : t == CAMP_RXN_CUSTOM_OH_HNO3 ? KR_OHHNO3 : KR_TUNNEL);
+        for (int v = 0; v < 9; ++v) s.v[v] = q.p[v];
+        s.v[9] = std::pow(kAvogadro * 1.0e-6, q.n_react - 1);
+      } else if (t == CAMP_RXN_ARRHENIUS) {
         if (q.p[0] < 0 || (q.p[2] != 0.0 && !(q.p[3] > 0))) {
           err << "reaction " << r << ": Arrhenius needs A >= 0 and D > 0 when B != 0";
           return err.str();
@@ -474,6 +503,70 @@ std::string compile_mechanism(const camp_reaction* rxns, int n_rxn, const camp_s
         xs.push_back(x);
         rs.push_back(s);
       }
+    } else if (t == CAMP_RXN_AQUEOUS_REVERSIBLE) {
+      const int p = q.phase;
+      if (p < 0 || p >= n_ph) {
+        err << "reaction " << r << ": aqueous reversible reaction needs a valid phase";
+        return err.str();
+      }
+      for (int k = 0; k < q.n_react; ++k)
+        if (sp_phase[q.react[k]] != p) {
+          err << "reaction " << r << ": reactant not in the reaction's phase";
+          return err.str();
+        }
+      for (int k = 0; k < q.n_prod; ++k)
+        if (sp_phase[q.prod[k]] != p || q.yield[k] != 1.0) {
+          err << "reaction " << r << ": reversible products must be in the phase with yield 1";
+          return err.str();
+        }
+      if (q.n_react < 1 || q.n_prod < 1 || q.p[0] < 0 || q.p[2] < 0) {
+        err << "reaction " << r << ": reversible reaction needs reactants, products, A >= 0, k_r >= 0";
+        return err.str();
+      }
+      // the reverse direction: products -> reactants, repeated reactants as yields
+      int rv_prod[3], rv_n = 0;
+      double rv_yld[3];
+      for (int k = 0; k < q.n_react; ++k) {
+        int f = -1;
+        for (int m = 0; m < rv_n; ++m)
+          if (rv_prod[m] == q.react[k]) f = m;
+        if (f < 0) {
+          rv_prod[rv_n] = q.react[k];
+          rv_yld[rv_n++] = 1.0;
+        } else {
+          rv_yld[f] += 1.0;
+        }
+      }
+      for (int i = 0; i < ph[p].n_instances; ++i)
+        for (int dir = 0; dir < 2; ++dir) {
+          RateSpec s = base_spec(dir == 0 ? KR_AQREV_FWD : KR_AQREV_REV);
+          s.inst = phase_first_inst[p] + i;
+          s.v[0] = q.p[0];
+          s.v[1] = q.p[1];
+          s.v[2] = q.p[2];
+          s.v[3] = ph[p].density_kg_m3;
+          X x{};
+          if (dir == 0) {
+            x.nr = q.n_react;
+            x.np = q.n_prod;
+            for (int k = 0; k < q.n_react; ++k) x.react[k] = cond_state(p, i, q.react[k]);
+            for (int k = 0; k < q.n_prod; ++k) {
+              x.prod[k] = cond_state(p, i, q.prod[k]);
+              x.yld[k] = 1.0;
+            }
+          } else {
+            x.nr = q.n_prod;
+            x.np = rv_n;
+            for (int k = 0; k < q.n_prod; ++k) x.react[k] = cond_state(p, i, q.prod[k]);
+            for (int k = 0; k < rv_n; ++k) {
+              x.prod[k] = cond_state(p, i, rv_prod[k]);
+              x.yld[k] = rv_yld[k];
+            }
+          }
+          s.nr = x.nr;
+          xs.push_back(x);
+          rs.push_back(s);
+        }
     } else if (t == CAMP_RXN_HENRY_TRANSFER || t == CAMP_RXN_SIMPOL_TRANSFER) {
       const int p = q.phase;
       if (p < 0 || p >= n_ph) {
@@ -568,6 +661,7 @@ std::string compile_mechanism(const camp_reaction* rxns, int n_rxn, const camp_s
     for (const X& x : xs) n_part += x.nr;
     // Gauss-Jordan keeps 4K doubles in the partials / rates scratch of a cell
     const int scratch_k = (int)(std::max<long long>(n_part, (long long)xs.size()) / 4);
+    C.nnz_lu = (int)nnz;
     C.tail_k = choose_tail(N, F, nnz, std::min(max_tail(4), scratch_k));
     if (C.tail_k > 0) F = with_dense_tail(F, N, C.tail_k);
   }
@@ -1011,6 +1105,9 @@ StageBlock build_stage_block(const Compiled& C, int wave_lists, bool use_tail) {
     sb.n_tail = (int)te.size();
     sb.off_tail = put(te.data(), 4 * te.size());
     sb.off_tail_lp = put(tp.data(), 4 * tp.size());
+    std::vector<uint16_t> rs(K);
+    for (int i = 0; i < K; ++i) rs[i] = (uint16_t)(C.row_ptr[ts + i + 1] - K);
+    sb.off_tail_rs = put(rs.data(), 2 * rs.size());
   }
   b.resize((b.size() + 15) / 16 * 16);
   sb.core_bytes = (int)b.size();
@@ -1091,7 +1188,11 @@ bool emulate_factor_solve(const Compiled& C, const StageBlock& sb, double* M, do
   std::vector<int> slot((size_t)K * K);
   for (int i = 0; i < sb.n_tail; ++i) {
     const uint32_t e = u32(sb.off_tail, i);
-    slot[(size_t)((e >> 16) & 0xFF) * K + (e >> 24)] = (int)(e & 0xFFFF);
+    const int r = (e >> 16) & 0xFF, c = e >> 24;
+    uint16_t rs;
+    std::memcpy(&rs, sb.bytes.data() + sb.off_tail_rs + 2 * (size_t)r, 2);
+    if ((int)(e & 0xFFFF) != rs + c) return false;   // row-start table disagrees
+    slot[(size_t)r * K + c] = (int)(e & 0xFFFF);
   }
   for (int p = 0; p < K; ++p) {
     const double piv = M[slot[(size_t)p * K + p]];

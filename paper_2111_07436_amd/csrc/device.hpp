@@ -27,6 +27,7 @@ struct StageView {
   int wave_lists;   // per-wavefront term lists per level (1, 2 or 4)
   int n_lu_lev;     // factorization levels of this layout
   int tail_k, tail_s, so_tail, so_tail_lp, n_tail;   // dense tail (tail_k = 0: none)
+  int so_tail_rs;
 };
 
 // Device copies of the compiled tables; passed to kernels by value.
@@ -90,22 +91,50 @@ struct SolveParams {
 
 // BDF coefficients: gamma_q = sum_{j=1}^{q} 1/j; local error constant 1/(q+1).
 __device__ __forceinline__ double bdf_gamma(int q) {
-  double g = 0.0;
-  for (int j = 1; j <= q; ++j) g += 1.0 / j;
-  return g;
+  return q <= 1 ? 1.0 : q == 2 ? 1.5 : q == 3 ? 11.0 / 6.0 : q == 4 ? 25.0 / 12.0 : 137.0 / 60.0;
 }
 
 constexpr double kGasConstant = 8.314462618;  // J mol^-1 K^-1
 constexpr double kAtmPa = 101325.0;
 constexpr double kPi = 3.14159265358979323846;
 
-// Rate constant of expanded reaction `r` for one cell (paper table of Process classes).
+constexpr double kBoltzmann = 1.380649e-23;   // J K^-1
+
+// A exp(-Ea/T) (T/300)^B: the Arrhenius form with D = 300 K and E = 0 that the fall-off
+// and custom forms are built from.
+__device__ __forceinline__ double arrhenius300(const double* a, double T) {
+  double k = a[0] * exp(-a[1] / T);
+  if (a[2] != 0.0) k *= pow(T / 300.0, a[2]);
+  return k;
+}
+
+// Rate constant of expanded reaction `r` for one cell (paper tables of Process classes).
 // Phase-instance rates are zero when the instance has no mass.
 __device__ inline double rate_constant(const DevMech& m, int r, double T, double P, double cosz,
                                        const double* radius, const double* mass,
                                        const double* ovr) {
   const int kind = m.rs_kind[r];
   const double* v = m.rs_v + (size_t)r * 12;
+  // number density of air, molecule cm^-3
+  const double air = P / (kBoltzmann * T) * 1.0e-6;
+  switch (kind) {
+    case 10: {  // Troe fall-off
+      const double k0m = arrhenius300(v, T) * air, kinf = arrhenius300(v + 3, T);
+      const double lg = log10(k0m / kinf);
+      const double k = k0m / (1.0 + k0m / kinf) * pow(v[6], 1.0 / (1.0 + lg * lg / v[7]));
+      return k * v[9];
+    }
+    case 11:    // HO2 self-reaction: k1 + k2 [M]
+      return (arrhenius300(v, T) + arrhenius300(v + 3, T) * air) * v[9];
+    case 12: {  // OH + HNO3: k0 + k3[M] / (1 + k3[M] / k2)
+      const double k3m = arrhenius300(v + 6, T) * air;
+      return (arrhenius300(v, T) + k3m / (1.0 + k3m / arrhenius300(v + 3, T))) * v[9];
+    }
+    case 13:    // tunneling: A exp(-B/T) exp(C/T^3)
+      return v[0] * exp(-v[1] / T) * exp(v[2] / (T * T * T)) * v[9];
+    default:
+      break;
+  }
   switch (kind) {
     case 1: {  // Arrhenius, already scaled to mol m^-3 units
       double k = v[0] * exp(-v[1] / T);
@@ -129,6 +158,14 @@ __device__ inline double rate_constant(const DevMech& m, int r, double T, double
   const int g = m.rs_inst[r];
   const double ms = mass[g];
   if (ms == 0.0) return 0.0;
+  if (kind == 14 || kind == 15) {  // aqueous reversible: forward K k_r, reverse k_r, on molarities
+    const int nr = m.rs_nr[r];
+    const double vol = ms / v[3];
+    double k = v[2];
+    if (kind == 14) k *= v[0] * exp(v[1] * (1.0 / T - 1.0 / 298.0));
+    if (nr != 1) k *= pow(1000.0 * vol, (double)(1 - nr));
+    return k;
+  }
   if (kind == 5) {  // condensed-phase Arrhenius
     double k = v[0] * exp(-v[1] / T);
     if (v[2] != 0.0) k *= pow(T / v[3], v[2]);
@@ -171,6 +208,14 @@ __device__ __forceinline__ double dpp_move(double v) {
 // The value of `v` held by lane `l` (a compile-time constant), as a wavefront-uniform value.
 template <int l>
 __device__ __forceinline__ double lane_value(double v) {
+  const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)b, l);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), l);
+  return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+
+// The value of `v` held by lane `l` (wavefront-uniform; l need not be a constant).
+__device__ __forceinline__ double lane_double(double v, int l) {
   const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
   const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)b, l);
   const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), l);

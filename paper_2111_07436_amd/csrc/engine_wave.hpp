@@ -171,6 +171,33 @@ __device__ __forceinline__ void for_terms_split(int lo, int hi, int lane, Entry 
 
 constexpr int kTermBatch = 4;
 
+// Product terms i = lo + lane, lo + lane + 64, ... < hi of one wavefront's list, in groups of
+// kU per lane: the table entries of a group first, then the two LDS operands of each
+// (operands(e) -> double2), then the updates (apply(e, operands)), phases held apart by
+// scheduling barriers so a group costs one table and one LDS round trip. Only valid where
+// no term of the list reads what another writes.
+template <int kU, class Entry, class Operands, class Apply>
+__device__ __forceinline__ void product_group(int i, Entry entry, Operands operands, Apply apply) {
+  uint2 e[kU];
+#pragma unroll
+  for (int u = 0; u < kU; ++u) e[u] = entry(i + u * kWave);
+  __builtin_amdgcn_sched_barrier(0);
+  double2 v[kU];
+#pragma unroll
+  for (int u = 0; u < kU; ++u) v[u] = operands(e[u]);
+  __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+  for (int u = 0; u < kU; ++u) apply(e[u], v[u]);
+}
+template <int kU, class Entry, class Operands, class Apply>
+__device__ __forceinline__ void for_products(int lo, int hi, int lane, Entry entry, Operands operands,
+                                             Apply apply) {
+  int i = lo + lane;
+  for (; i + (kU - 1) * kWave < hi; i += kU * kWave) product_group<kU>(i, entry, operands, apply);
+  for (; i + kWave < hi; i += 2 * kWave) product_group<2>(i, entry, operands, apply);
+  for (; i < hi; i += kWave) product_group<1>(i, entry, operands, apply);
+}
+
 // Level pointers of a term list held in registers: lane k holds entry k and entry k + 64,
 // so reading the bounds of a level is a lane read instead of an LDS round trip. Lists of
 // more than 127 levels read the rest from the table.
@@ -252,6 +279,7 @@ struct Tabs {
   __device__ uint32_t us(int i) const { return reinterpret_cast<const uint32_t*>(b + v.so_us)[i]; }
   __device__ uint32_t tl(int i) const { return reinterpret_cast<const uint32_t*>(b + v.so_tail)[i]; }
   __device__ int tl_lp(int a) const { return (int)reinterpret_cast<const uint32_t*>(b + v.so_tail_lp)[a]; }
+  __device__ int tl_rs(int i) const { return reinterpret_cast<const uint16_t*>(b + v.so_tail_rs)[i]; }
 };
 
 template <int NPL, int G>
@@ -261,6 +289,11 @@ struct WaveCell {
   static constexpr int kLevelBatch = NPL >= 4 ? 4 : 1;
   // Levels whose first table entries are read together (sweeps, LU).
   static constexpr int kWindow = (G == kWave && NPL <= 2) ? 2 : 8;
+  // Dense-tail entries per lane (see tail_invert; max_tail bounds K to fit).
+  static constexpr int kTail = G == kWave ? kTailPerLaneOneWave : kTailPerLane;
+  // Product terms per lane issued together beyond a level's first (registers are tightest
+  // in the one-wavefront kernels of at most two species per lane).
+  static constexpr int kProdBatch = (G == kWave && NPL <= 2) ? 2 : kTermBatch;
   const DevMech& m;
   Tabs tb;
   double* M;
@@ -425,7 +458,10 @@ struct WaveCell {
           if (l0 + u >= L) break;
           const int i = r[u].x + wlane();
           if (i < r[u].y) prod(e[u]);
-          for (int k = i + kWave; k < r[u].y; k += kWave) prod(tb.lt(k));
+          for_products<kProdBatch>(
+              r[u].x + kWave, r[u].y, wlane(), [&](int k) { return tb.lt(k); },
+              [&](const uint2& t) { return make_double2(M[t.x >> 16], M[t.y]); },
+              [&](const uint2& t, const double2& v) { lds_add(&M[t.x & 0xFFFF], -(v.x * v.y)); });
           sync();
           if (fb[u] == fb[u + 1]) continue;
           const int j = fb[u] + lane;
@@ -472,27 +508,31 @@ struct WaveCell {
 
   // Dense tail: inverts the trailing K x K block in place (it holds the Schur complement S
   // after the levels) by Gauss-Jordan elimination without pivoting, one group barrier per
-  // step. A lane keeps its tail entries (whole rows per wavefront) in registers; step p
-  // reads row p and column p of the current matrix from a copy in LDS (P: two sets of a row
-  // and a column, alternating), and the lanes that write the new row and column p + 1 also
-  // write the other set. Returns nonzero if a pivot is zero or not finite.
+  // step. Wavefront w of the group owns the block rows i = w, w + kW, ...; its lanes form
+  // max(1, 64 / K) groups of K, lane j of group g holding column j of the wavefront's rows
+  // g, g + groups, ... in registers for all K steps. Step p needs row p and column p of the
+  // current matrix: a copy of each sits in LDS (P, two sets alternating), and the lanes whose
+  // new values form row and column p + 1 write them to the other set. With one lane group,
+  // the column values of the wavefront's rows are read once and passed by lane reads.
+  // Returns nonzero if a pivot is zero or not finite.
   __device__ __forceinline__ int tail_invert() const {
     const int K = tb.v.tail_k;
-    const int lo = uniform(tb.tl_lp(wid())), hi = uniform(tb.tl_lp(wid() + 1));
-    uint32_t e[kTailPerLane];
+    const int w = wid(), l = wlane();
+    const int groups = K <= kWave / 2 ? kWave / K : 1;
+    const int g = l / K, j = l - g * K;
+    const int rows = (K - w + kW - 1) / kW;             // rows of this wavefront
+    const int n_t = g < groups ? (rows - g + groups - 1) / groups : 0;   // entries of this lane
+    // block row of the lane's entry t
+    auto row = [&](int t) { return w + kW * (g + groups * t); };
+    double a[kTail];
 #pragma unroll
-    for (int u = 0; u < kTailPerLane; ++u) {
-      const int i = lo + wlane() + kWave * u;
-      e[u] = i < hi ? tb.tl(i) : 0xFFFFFFFFu;
-    }
+    for (int t = 0; t < kTail; ++t) a[t] = t < n_t ? M[tb.tl_rs(row(t)) + j] : 0.0;
     // row 0 and column 0 of S into set 0
 #pragma unroll
-    for (int u = 0; u < kTailPerLane; ++u) {
-      if (e[u] == 0xFFFFFFFFu) continue;
-      const int i = (e[u] >> 16) & 0xFF, j = e[u] >> 24;
-      const double v = M[e[u] & 0xFFFF];
-      if (i == 0) P[j] = v;
-      if (j == 0) P[K + i] = v;
+    for (int t = 0; t < kTail; ++t) {
+      if (t >= n_t) continue;
+      if (row(t) == 0) P[j] = a[t];
+      if (j == 0) P[K + row(t)] = a[t];
     }
     sync();
     int bad = 0;
@@ -502,23 +542,44 @@ struct WaveCell {
       double* rn = P + ((p + 1) & 1) * 2 * K;          // row p + 1 (next set)
       double* cn = rn + K;                             // column p + 1
       const double piv = rp[p];
+      const double rj = rp[n_t > 0 ? j : 0];
       if (!(fabs(piv) > 0.0) || !isfinite(piv)) bad = 1;
       const double r = 1.0 / piv;
+      // every entry slot is updated (fully unrolled, registers indexed by constants); slots
+      // beyond the lane's entries hold unused values
+      auto update = [&](int t, double ci) {
+        const int i = row(t);
+        const double off = i == p ? rj * r : a[t] - ci * rj * r;
+        a[t] = j == p ? (i == p ? r : -ci * r) : off;
+      };
+      if (groups == 1) {
+        const double cr = cp[l < rows ? w + kW * l : 0];
 #pragma unroll
-      for (int u = 0; u < kTailPerLane; ++u) {
-        if (e[u] == 0xFFFFFFFFu) continue;
-        const int i = (e[u] >> 16) & 0xFF, j = e[u] >> 24;
-        double* a = &M[e[u] & 0xFFFF];
-        double v;
-        if (i == p) v = j == p ? r : rp[j] * r;
-        else if (j == p) v = -cp[i] * r;
-        else v = *a - cp[i] * rp[j] * r;
-        *a = v;
-        if (j == p + 1) cn[i] = v;
-        if (i == p + 1) rn[j] = v;
+        for (int t = 0; t < kTail; ++t) update(t, lane_double(cr, t));
+      } else {
+#pragma unroll
+        for (int t = 0; t < kTail; ++t) update(t, cp[t < n_t ? row(t) : 0]);
+      }
+      // row p + 1: at most one entry of this lane; column p + 1: lane j = p + 1's entries
+      double vr = 0.0;
+      int wr = 0;
+#pragma unroll
+      for (int t = 0; t < kTail; ++t)
+        if (t < n_t && row(t) == p + 1) {
+          vr = a[t];
+          wr = 1;
+        }
+      if (wr) rn[j] = vr;
+      if (j == p + 1) {
+#pragma unroll
+        for (int t = 0; t < kTail; ++t)
+          if (t < n_t) cn[row(t)] = a[t];
       }
       sync();
     }
+#pragma unroll
+    for (int t = 0; t < kTail; ++t)
+      if (t < n_t) M[tb.tl_rs(row(t)) + j] = a[t];
     return bad;
   }
 
@@ -579,7 +640,10 @@ struct WaveCell {
           if (l0 + u >= nlev) break;
           const int i = r[u].x + wlane();
           if (i < r[u].y) term(e[u]);
-          for (int j = i + kWave; j < r[u].y; j += kWave) term(ent(j));
+          for_products<kProdBatch>(
+              r[u].x + kWave, r[u].y, wlane(), ent,
+              [&](const uint2& t) { return make_double2(M[t.y], xl[t.x >> 16]); },
+              [&](const uint2& t, const double2& v) { lds_add(&xl[t.x & 0xFFFF], -(v.x * v.y)); });
           sync();
         }
       }
@@ -738,7 +802,7 @@ __device__ __forceinline__ int integrate(const DevMech& m, double* yrow, const S
       if (++attempts > sp.max_steps) { status = ST_MAX_STEPS; break; }
       if (step_collapsed(h, t, sp.h_min)) { status = ST_H_MIN; break; }
       const double gq = bdf_gamma(q);
-      const double c = h / gq;
+      const double c = h / gq, inv_gq = 1.0 / gq;
       double psi[NPL], yv[NPL];
 #pragma unroll
       for (int i = 0; i < NPL; ++i) {
@@ -751,7 +815,7 @@ __device__ __forceinline__ int integrate(const DevMech& m, double* yrow, const S
             ps += g * D[j][i];
           }
         }
-        psi[i] = ps / gq;
+        psi[i] = ps * inv_gq;
         yv[i] = s;
         d[i] = 0.0;
         const int tt = lane + G * i;
@@ -871,8 +935,9 @@ __device__ __forceinline__ int integrate(const DevMech& m, double* yrow, const S
         continue;
       }
       double dq1[NPL];
+      const double inv_q1 = 1.0 / (q + 1);
 #pragma unroll
-      for (int i = 0; i < NPL; ++i) dq1[i] = d[i] / (q + 1);
+      for (int i = 0; i < NPL; ++i) dq1[i] = d[i] * inv_q1;
       err = W.wrms(dq1, w);
       if (err > 1.0) {
         cs.rejected++;

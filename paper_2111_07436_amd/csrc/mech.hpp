@@ -21,7 +21,13 @@ enum RateKind : int {
   KR_HENRY_COND = 6,
   KR_HENRY_EVAP = 7,
   KR_SIMPOL_COND = 8,
-  KR_SIMPOL_EVAP = 9
+  KR_SIMPOL_EVAP = 9,
+  KR_TROE = 10,
+  KR_H2O2 = 11,
+  KR_OHHNO3 = 12,
+  KR_TUNNEL = 13,
+  KR_AQREV_FWD = 14,
+  KR_AQREV_REV = 15
 };
 
 constexpr int kRateParams = 12;
@@ -33,6 +39,9 @@ constexpr int kRateParams = 12;
 //   CONDENSED : v = {A, Ea/kb, B, D, E, aqueous, density}
 //   *_COND/*_EVAP: v = {D_g, MW_g, alpha, density, mw_absorber, p0..p3}
 //                  Henry p = {H298, C}, SIMPOL p = {B1, B2, B3, B4}
+//   TROE, H2O2, OHHNO3, TUNNEL: v[0..8] = the process parameters p[0..8], v[9] = the unit
+//                  factor (N_A 1e-6)^(n_r-1) from molecule cm^-3 to mol m^-3
+//   AQREV_FWD/REV: v = {A, C, k_r, density}
 struct RateSpec {
   int kind;
   int ext;    // column of rate_override, or -1
@@ -58,6 +67,7 @@ struct Compiled {
   // their factorization and triangular solves by the explicit inverse of their Schur
   // complement (see StageBlock).
   int tail_k = 0;
+  int nnz_lu = 0;   // entries of the symbolic LU fill (before the dense tail is added)
 
   // phase instance -> phase, first state index (user order)
   std::vector<int> inst_phase, inst_base;
@@ -128,7 +138,8 @@ struct Compiled {
 // M[slot] x[s + j]); head rows scaled by their reciprocal pivots, x[s + i] = t[i]; backward
 // sweep over the head rows. This replaces the tail's chain of one-row sweep levels by one
 // level. The tail terms are stored as W per-wavefront lists, whole rows per list, with
-// pointers u32 [W + 1]; LU levels of the layout: n_lu_lev.
+// pointers u32 [W + 1]; the tail row i's columns are the slots rs[i] .. rs[i] + K - 1
+// (u16 [K]); LU levels of the layout: n_lu_lev.
 //
 // The block has a core part (the above) followed by an extension with the forcing terms
 // (u32 {species | reaction << 16}, coef f64) and the Jacobian contributions
@@ -147,12 +158,16 @@ struct StageBlock {
   int wave_lists = 1;
   int n_lu_lev = 0;
   int tail_k = 0, tail_s = 0, off_tail = 0, off_tail_lp = 0, n_tail = 0;
+  int off_tail_rs = 0;   // u16 [K]: slot of the first tail column of tail row i
   bool ok = false;   // false when the mechanism exceeds the 16-bit index ranges
 };
 
-// Largest dense tail a layout supports: every wavefront holds at most kTailPerLane tail
-// terms per lane (whole rows per wavefront), and Gauss-Jordan needs 4K doubles of scratch.
-constexpr int kTailPerLane = 8;
+// Largest dense tail a layout supports. Gauss-Jordan gives wavefront w of W the rows
+// i = w, w + W, ...; its lanes are split into max(1, 64 / K) groups of K lanes, lane j of a
+// group owning column j of every group-th row; a lane holds at most kTailPerLane entries.
+// It also needs 4K doubles of scratch.
+constexpr int kTailPerLane = 12;
+constexpr int kTailPerLaneOneWave = 4;   // one wavefront per cell: registers are tighter
 int max_tail(int wave_lists);
 
 // wave_lists: per-wavefront term lists per level, 1 (one wavefront per cell), 2 or 4 (one

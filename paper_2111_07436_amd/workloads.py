@@ -38,6 +38,11 @@ RXN_FIRST_ORDER_LOSS = 4     # p = [k (s^-1)]
 RXN_CONDENSED_ARRHENIUS = 5  # p = [A, Ea/kb (K), B, D (K), E (Pa^-1), aqueous_flag]
 RXN_HENRY_TRANSFER = 6       # p = [H298 (M Pa^-1), C (K)]
 RXN_SIMPOL_TRANSFER = 7      # p = [B1, B2, B3, B4]
+RXN_TROE = 8                 # p = [A0, Ea0/kb, B0, Ainf, Eainf/kb, Binf, Fc, N]
+RXN_CUSTOM_H2O2 = 9          # p = [A1, Ea1/kb, B1, A2, Ea2/kb, B2]
+RXN_CUSTOM_OH_HNO3 = 10      # p = [A0, Ea0/kb, B0, A2, Ea2/kb, B2, A3, Ea3/kb, B3]
+RXN_WENNBERG_TUNNELING = 11  # p = [A, B (K), C (K^3)]
+RXN_AQUEOUS_REVERSIBLE = 12  # p = [A (K_eq at 298 K), C (K), k_r]
 
 EXTERNAL_TYPES = (RXN_PHOTOLYSIS, RXN_EMISSION, RXN_FIRST_ORDER_LOSS)
 
@@ -66,7 +71,7 @@ class Reaction:
     react: List[int] = field(default_factory=list)
     prod: List[int] = field(default_factory=list)
     yields: List[float] = field(default_factory=list)
-    p: List[float] = field(default_factory=lambda: [0.0] * 6)
+    p: List[float] = field(default_factory=lambda: [0.0] * 10)
     phase: int = -1                 # condensed / transfer reactions: the phase index
 
 
@@ -387,12 +392,71 @@ AEROSOL_RECIPES = {
     "c3": AerosolRecipe(n_phases=6, n_sections=4, species_per_phase=5, aq_per_phase=20),
     "c5": AerosolRecipe(n_phases=10, n_sections=8, species_per_phase=4, aq_per_phase=10),
 }
-CELLS = {"c1": 100, "c2": 10_000, "c3": 100_000, "c5": 500_000}
+CELLS = {"c1": 100, "c2": 10_000, "c3": 100_000, "c5": 500_000, "zoo": 256}
+
+
+def gen_rate_type_zoo(rng) -> Mechanism:
+    """A small mechanism with every process type: gas-phase Arrhenius, photolysis,
+    emission, first-order loss, Troe fall-off, HO2 self-reaction, OH + HNO3, tunneling, and
+    an aqueous phase of 3 instances with Henry's-law and SIMPOL transfer, condensed-phase
+    Arrhenius and reversible reactions. Parameters are drawn from ranges typical of
+    tropospheric kinetics (pre-exponential factors in molecule cm^-3 units)."""
+    lu = lambda lo, hi: float(np.exp(rng.uniform(np.log(lo), np.log(hi))))
+    g = [Species(name=f"Z{i}", phase=-1, mw=float(rng.uniform(0.03, 0.2)),
+                 diff=float(rng.uniform(0.8e-5, 2.0e-5)), accom=float(rng.uniform(0.05, 0.5)))
+         for i in range(12)]
+    aq = [Species(name=f"AQ{i}", phase=0) for i in range(5)]
+    species = g + aq
+    A0, A1, A2, A3, A4 = 12, 13, 14, 15, 16
+    phases = [Phase("aqueous", [A0, A1, A2, A3, A4], 3, density=1000.0, mw_absorber=0.1)]
+
+    def arr3():
+        return [lu(1e-13, 1e-11), float(rng.uniform(-600.0, 600.0)), float(rng.uniform(-1.5, 0.0))]
+
+    rx = [
+        Reaction(RXN_ARRHENIUS, [0, 1], [2], [1.0], [lu(1e-13, 1e-11), float(rng.uniform(0, 1500)), 0, 300, 0, 0]),
+        Reaction(RXN_ARRHENIUS, [2], [3, 4], [1.0, 1.0], [lu(1e-4, 1e-2), 0, 0, 300, 0, 0]),
+        Reaction(RXN_PHOTOLYSIS, [3], [0, 5], [1.0, 1.0], [lu(1e-4, 1e-2), 1.0, 0, 0, 0, 0]),
+        Reaction(RXN_EMISSION, [], [0], [1.0], [lu(1e-12, 1e-10), 0, 0, 0, 0, 0]),
+        Reaction(RXN_EMISSION, [], [6], [1.0], [lu(1e-12, 1e-10), 0, 0, 0, 0, 0]),
+        Reaction(RXN_FIRST_ORDER_LOSS, [4], [], [], [lu(1e-5, 1e-3), 0, 0, 0, 0, 0]),
+        # Troe: three-body association, low- and high-pressure limits
+        Reaction(RXN_TROE, [5, 1], [7], [1.0],
+                 [lu(1e-31, 1e-29), 0.0, float(rng.uniform(-4.0, -1.0)), lu(1e-12, 1e-10), 0.0,
+                  float(rng.uniform(-1.0, 0.0)), 0.6, 1.0, 0, 0]),
+        Reaction(RXN_TROE, [6, 1], [8], [1.0],
+                 [lu(1e-31, 1e-29), 0.0, float(rng.uniform(-4.0, -1.0)), lu(1e-12, 1e-10), 0.0,
+                  float(rng.uniform(-1.0, 0.0)), float(rng.uniform(0.3, 0.7)), 1.0, 0, 0]),
+        # HO2-like self-reaction with a pressure-dependent term
+        Reaction(RXN_CUSTOM_H2O2, [9, 9], [10], [1.0],
+                 [lu(1e-13, 1e-12), float(rng.uniform(-700, -300)), 0.0, lu(1e-33, 1e-32),
+                  float(rng.uniform(-1100, -700)), 0.0, 0, 0, 0, 0]),
+        # OH + HNO3-like
+        Reaction(RXN_CUSTOM_OH_HNO3, [1, 11], [5], [1.0],
+                 [lu(1e-14, 1e-13), float(rng.uniform(-900, -700)), 0.0, lu(1e-17, 1e-16),
+                  float(rng.uniform(-2500, -2000)), 0.0, lu(1e-34, 1e-33),
+                  float(rng.uniform(-1200, -900)), 0.0, 0]),
+        # tunneling isomerization
+        Reaction(RXN_WENNBERG_TUNNELING, [7], [9], [1.0],
+                 [lu(1e6, 1e9), float(rng.uniform(5000, 6000)), float(rng.uniform(1e7, 1e8)), 0, 0, 0, 0, 0, 0, 0]),
+        Reaction(RXN_ARRHENIUS, [10], [11], [1.0], [lu(1e-5, 1e-3), 0, 0, 300, 0, 0]),
+        Reaction(RXN_PHOTOLYSIS, [8], [6, 9], [1.0, 1.0], [lu(1e-5, 1e-3), 0.0, 0, 0, 0, 0]),
+        # aqueous phase
+        Reaction(RXN_HENRY_TRANSFER, [2], [A0], [1.0], [lu(1e-4, 1e-2), float(rng.uniform(1000, 3000)), 0, 0, 0, 0], phase=0),
+        Reaction(RXN_SIMPOL_TRANSFER, [8], [A2], [1.0], [float(rng.uniform(3.0e3, 4.5e3)), float(rng.uniform(-23, -19)), 0, 0, 0, 0], phase=0),
+        Reaction(RXN_AQUEOUS_REVERSIBLE, [A0], [A1], [1.0], [lu(0.5, 20.0), float(rng.uniform(-2000, 2000)), lu(1e-3, 1e-1), 0, 0, 0, 0, 0, 0, 0], phase=0),
+        Reaction(RXN_AQUEOUS_REVERSIBLE, [A2, A2], [A3], [1.0], [lu(0.1, 10.0), float(rng.uniform(-2000, 2000)), lu(1e-3, 1e-1), 0, 0, 0, 0, 0, 0, 0], phase=0),
+        Reaction(RXN_CONDENSED_ARRHENIUS, [A1, A3], [A4], [1.0], [lu(0.1, 10.0), 0, 0, 300, 0, 1.0], phase=0),
+    ]
+    return Mechanism(species=species, phases=phases, reactions=rx)
 
 
 def make_mechanism(name: str, seed: int = 0) -> Mechanism:
-    """The mechanism of a named config ("c1", "c2", "c3" or "c5")."""
+    """The mechanism of a named config ("c1", "c2", "c3" or "c5"), or the rate-type test
+    mechanism "zoo"."""
     rng = np.random.Generator(np.random.PCG64(seed))
+    if name == "zoo":
+        return gen_rate_type_zoo(rng)
     gas_key = {"c1": "c1", "c2": "c2", "c3": "c2", "c5": "c5"}[name]
     species, rxns, w, organics = gen_gas_mechanism(rng, GAS_RECIPES[gas_key])
     phases = []
@@ -417,6 +481,9 @@ def make_workload(name: str, n_cells: Optional[int] = None, seed: int = 0) -> Wo
     elif name == "c5":
         env = gen_env(rng, mech, C, (200.0, 320.0), (2.0e4, 1.013e5), sza=True)
         dt, calls = 3600.0, 1
+    elif name == "zoo":
+        env = gen_env(rng, mech, C, (230.0, 310.0), (2.0e4, 1.013e5), sza=True)
+        dt, calls = 600.0, 1
     else:
         raise ValueError(name)
     y0 = gen_y0(rng, mech, env)

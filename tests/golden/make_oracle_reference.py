@@ -1,11 +1,11 @@
 """Writes oracle reference states for sampled cells of the large workloads.
 
-The oracle (CPU FP64 BDF with full Newton and dense LU) needs minutes per cell on the
-largest mechanism, too long to run inside a test, so the GPU parity tests for those
-workloads compare against values this script stores. It calls only `oracle/` and the
+The GPU parity tests of the full-size workloads and the benchmark's accuracy figures compare
+against oracle states this script stores (the oracle, a CPU FP64 BDF with full Newton and
+dense LU, needs seconds to minutes per cell at rtol 1e-10). It calls only `oracle/` and the
 seeded workload generator; nothing here comes from the GPU path.
 
-Usage: python tests/golden/make_oracle_reference.py [c3|c5 ...]
+Usage: python tests/golden/make_oracle_reference.py [c1|c2|c3|c5 ...]
 Writes tests/golden/oracle_<workload>.json: workload, n_cells, sampled cells, tolerances,
 the oracle's final states (user species order) and statuses.
 """
@@ -27,6 +27,8 @@ RTOL, ATOL = 1e-10, 1e-20
 # last cells, cells spread evenly over the rest, and zero-aerosol cells (C3 cells 1 and 5, C5 cells
 # 2 and 3 have no aerosol mass in the seeded draws).
 SAMPLES = {
+    "c1": (100, [0, 9, 18, 27, 36, 45, 54, 63, 72, 81, 90, 99]),
+    "c2": (10_000, [int(c) for c in np.linspace(0, 9_999, 16)]),
     "c3": (100_000, [0, 1, 2, 5, 25_000, 50_000, 75_000, 99_999]),
     "c5": (500_000, [0, 2, 3] + [int(c) for c in np.linspace(38_461, 461_538, 12)] + [499_999]),
 }

@@ -69,6 +69,22 @@ def test_c3_multiphase_sample(torch, engine):
     assert np.all(y[zero, ng:] == 0.0)
 
 
+@pytest.mark.parametrize("engine", ENGINES)
+def test_rate_type_zoo(torch, engine):
+    """Every process type (Troe, custom H2O2 and OH + HNO3, tunneling, aqueous reversible,
+    transfer, condensed-phase, photolysis, emission, loss) in one mechanism."""
+    from paper_2111_07436_amd import camp
+    wl = W.make_workload("zoo", n_cells=100)
+    m = camp.Mech(wl.mech)
+    log(f"zoo engine {engine}: {wl.n_cells} cells, dt {wl.dt}")
+    y = gpu_solve(m, wl, engine)
+    zero = np.all(wl.env.mass == 0.0, axis=1)
+    sample = [int(np.nonzero(zero)[0][0]), int(np.nonzero(~zero)[0][0]), 50, 99]
+    yr, st, _ = oracle_solve(wl.mech, wl.env, wl.y0, wl.dt, 1, OR_RTOL, OR_ATOL, cells=sample)
+    assert np.all(st == 0)
+    assert_parity(y[sample], yr, what=f"zoo/{engine}")
+
+
 def test_c2_full_size_sampled(torch):
     """All 10,000 cells of the realistic gas config in the benchmark's launch configuration."""
     from paper_2111_07436_amd import camp

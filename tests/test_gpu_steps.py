@@ -24,11 +24,11 @@ def torch():
     return require_gpu()
 
 
-@pytest.fixture(scope="module", params=["c1", "c2", "c3", "c5"])
+@pytest.fixture(scope="module", params=["c1", "c2", "c3", "c5", "zoo"])
 def setup(request, torch):
     from paper_2111_07436_amd import camp
     name = request.param
-    n = {"c1": 100, "c2": 130, "c3": 130, "c5": 70}[name]      # ragged: not multiples of 64
+    n = {"c1": 100, "c2": 130, "c3": 130, "c5": 70, "zoo": 100}[name]   # ragged: not multiples of 64
     wl = W.make_workload(name, n_cells=n)
     m = camp.Mech(wl.mech)
     x = expand(wl.mech)

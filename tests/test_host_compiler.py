@@ -20,14 +20,14 @@ def test_library_exports_every_declared_symbol():
     import ctypes
     import os
     hdr = open(os.path.join(os.path.dirname(__file__), "..", "include", "camp.h")).read()
-    declared = set(re.findall(r"^(?:int|void|const char\*)\s+(camp_[a-z_]+)\s*\(", hdr, re.M))
+    declared = set(re.findall(r"^(?:int|void|size_t|const char\*)\s+(camp_[a-z_]+)\s*\(", hdr, re.M))
     lib = ctypes.CDLL(camp.LIB_PATH)
     missing = [s for s in declared if not hasattr(lib, s)]
     assert not missing, missing
     assert declared == set(camp.EXPORTED)
 
 
-@pytest.mark.parametrize("name", ["c1", "c2", "c3", "c5"])
+@pytest.mark.parametrize("name", ["c1", "c2", "c3", "c5", "zoo"])
 def test_expansion_pattern_and_fill_match_oracle(name):
     mech = W.make_mechanism(name)
     m = camp.Mech(mech)

@@ -33,7 +33,7 @@ def random_system(m, rng, dominance=1.0):
     return vals, A
 
 
-@pytest.mark.parametrize("name", ["c1", "c2", "c3", "c5"])
+@pytest.mark.parametrize("name", ["c1", "c2", "c3", "c5", "zoo"])
 def test_table_program_solves_the_system(name, rng):
     m = camp.Mech(W.make_mechanism(name))
     vals, A = random_system(m, rng)
