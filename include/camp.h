@@ -28,6 +28,8 @@
 #ifndef CAMP_H
 #define CAMP_H
 
+#include <stddef.h>
+
 #ifdef __cplusplus
 extern "C" {
 #endif
@@ -311,6 +313,24 @@ int camp_plan_launch(camp_plan* plan, void* stream);
 
 /* Waits for the plan's device, then releases the graph and its scratch. NULL is ignored. */
 void camp_plan_free(camp_plan* plan);
+
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): camp_solve_device without any device
+ * allocation. Its scratch (queue counter and flags, rate-constant scratch, cell-order
+ * check counters) is a fixed array of camp_noalloc_scratch_bytes() (32 MiB) per GPU, held
+ * until the process ends. Requirements: the mechanism's tables already resident on the
+ * current device (a camp_solve_device or camp_plan_create with it on this device), and the
+ * fused wavefront engine (engine AUTO, which takes the autotuner's cached choice for this
+ * size bucket or else the occupancy default and never runs trials, or FUSED_WAVE). A solve
+ * that needs more scratch than the array holds is rejected with CAMP_EINVAL, as are the
+ * other engines. Every call on one GPU shares that GPU's array: calls that overlap on one
+ * GPU (other streams, other threads) race; serialize them. Results equal camp_solve_device's
+ * with the same launch choice. */
+int camp_solve_device_noalloc(camp_mech* mech, int n_cells, double* d_state,
+                              const camp_env* d_env, double dt, double rtol, double atol,
+                              const camp_opts* opts, int* d_cell_status,
+                              camp_cell_stats* d_cell_stats, void* stream);
+size_t camp_noalloc_scratch_bytes(void);
 
 /* --- Individual hot-path steps on device arrays (validation and composition). All
  *     per-cell arrays are row-major [cells][...] device memory. --- */

@@ -109,6 +109,9 @@ _sig = {
                                    C.c_double, C.POINTER(Opts), _P, _P, _P, C.POINTER(_P)]),
     "camp_plan_launch": (C.c_int, [_P, _P]),
     "camp_plan_free": (None, [_P]),
+    "camp_solve_device_noalloc": (C.c_int, [_P, C.c_int, _P, C.POINTER(Env), C.c_double, C.c_double,
+                                            C.c_double, C.POINTER(Opts), _P, _P, _P]),
+    "camp_noalloc_scratch_bytes": (C.c_size_t, []),
     "camp_serve_create": (C.c_int, [C.c_longlong, C.c_int, C.POINTER(_P)]),
     "camp_serve_submit": (C.c_int, [_P, _P, C.c_int, _P, C.POINTER(Env), C.c_double, C.c_double,
                                     C.c_double, C.POINTER(Opts), _P, C.POINTER(C.c_longlong)]),
@@ -294,6 +297,16 @@ class Mech:
         _check(_lib.camp_solve_device(self.h, n, _ptr(d_state), C.byref(e), dt, rtol, atol,
                                       None if opts is None else C.byref(opts), _ptr(d_status),
                                       _ptr(d_stats), _stream()))
+        return d_status
+
+    def solve_device_noalloc(self, denv, d_state, dt, rtol, atol, opts: Optional[Opts] = None,
+                             d_status=None, d_stats=None):
+        """camp_solve_device_noalloc on torch tensors (in place on d_state); d_status is
+        required (allocate it beforehand). Returns d_status."""
+        e = denv.c_env()
+        _check(_lib.camp_solve_device_noalloc(self.h, d_state.shape[0], _ptr(d_state), C.byref(e),
+                                              dt, rtol, atol, None if opts is None else C.byref(opts),
+                                              _ptr(d_status), _ptr(d_stats), _stream()))
         return d_status
 
     def rate_constants(self, denv, n_cells):
