@@ -42,13 +42,19 @@ WORKLOADS = {
     "c5": "large: 500,000 cells, 200 gas + 10 phases x 8 sections (520 state / 1720 reactions), 1 x 3600 s",
 }
 # Cells of the CPU-oracle sample (about 10-30 s on the host's share of cores).
-CPU_SAMPLE = {"c1": 100, "c2": 10000, "c3": 1024, "c5": 96}
+CPU_SAMPLE = {"c1": 100, "c2": 10000, "c3": 1024, "c5": 256}
 # The plain per-cell form runs on at most this many cells (the stored-oracle cells among them).
 PLAIN_CELLS = 16384
 # Tolerance at which the batched form meets the accuracy gate against the oracle (max
-# relative error <= 1e-4 above 1e-12 mol m^-3) on the stored sample, from a sweep of rtol with
-# atol = 1e-8 rtol; None: the configured tolerance passes.
-EQUAL_ACCURACY_TOL = {"c1": None, "c2": (1e-6, 1e-14), "c3": (1e-6, 1e-14), "c5": (1e-6, 1e-14)}
+# relative error <= 1e-4 above 1e-12 mol m^-3, <= 1e-12 absolute below) on the stored sample,
+# from a sweep of (rtol, atol) on the MI355X: with atol = 1e-8 rtol no rtol down to 1e-8
+# passes (species just above the floor stay atol-controlled); rtol 1e-7 with atol 1e-18 is
+# the loosest pair that passes on C2 and C5.
+EQUAL_ACCURACY_TOL = {"c1": (1e-7, 1e-18), "c2": (1e-7, 1e-18), "c3": (1e-7, 1e-18),
+                      "c5": (1e-7, 1e-18)}
+# The plain form at that tolerance runs on fewer cells (it is 100x slower than the batched
+# form); its rate in cell-steps/s is taken on the same stored-cell subset size as below.
+PLAIN_CELLS_EQUAL = 8192
 
 # HBM traffic of the dominant kernel per launch, from rocprofv3 --pmc FETCH_SIZE and
 # WRITE_SIZE runs of this script (KiB per dispatch), each scaled by the ratio of the known
@@ -195,17 +201,17 @@ def stats_mean(stats):
     return {f: float(s[:, i].mean()) for i, f in enumerate(camp.STATS_FIELDS)}
 
 
-def plain_subset(n_cells, stored_cells):
-    """The stored-oracle cells plus evenly strided others, at most PLAIN_CELLS in all."""
-    n = min(n_cells, PLAIN_CELLS)
+def plain_subset(n_cells, stored_cells, limit=PLAIN_CELLS):
+    """The stored-oracle cells plus evenly strided others, at most `limit` in all."""
+    n = min(n_cells, limit)
     extra = np.linspace(0, n_cells - 1, max(0, n - len(stored_cells))).astype(int)
     return np.unique(np.concatenate([stored_cells, extra])), n
 
 
-def run_plain(wl, rtol, atol, stored_cells, ref):
+def run_plain(wl, rtol, atol, stored_cells, ref, limit=PLAIN_CELLS):
     import torch
     from paper_2111_07436_amd import camp
-    cells, _ = plain_subset(wl.n_cells, stored_cells)
+    cells, _ = plain_subset(wl.n_cells, stored_cells, limit)
     keep = np.isin(stored_cells, cells)
     sub = wl.take(list(cells))
     m = camp.Mech(sub.mech)
@@ -504,13 +510,14 @@ def main():
             torch.cuda.synchronize()
             bsec = time.perf_counter() - t
             acc_b = accuracy(y.cpu().numpy()[stored[0]], stored[1])
-            p2 = run_plain(wl, rt, at, *stored)
+            p2 = run_plain(wl, rt, at, *stored, limit=PLAIN_CELLS_EQUAL)
             out["equal_accuracy"] = {
                 "rtol": rt, "atol": at, "value": cells / bsec, "plain_value": p2["value"],
                 "speedup_vs_plain": (cells / bsec) / p2["value"], "accuracy": acc_b,
                 "accuracy_plain": p2["accuracy"], "failed_cells": camp.count_failed(st),
+                "plain_cells": p2["cells"],
                 "what": "the configured rtol 1e-4 / atol 1e-12 does not meet the 1e-4 gate against "
-                        "the oracle; both forms at the tolerance where it does (atol = 1e-8 rtol)"}
+                        "the oracle; both forms at the loosest swept tolerance where it does"}
     if not args.no_graph:
         out["graph"] = run_graph_legs()
     if not args.no_served:

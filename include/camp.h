@@ -146,6 +146,27 @@ typedef struct camp_mech camp_mech;
 int camp_mech_load(const camp_reaction* rxns, int n_rxn, const camp_species* species,
                    int n_species, const camp_phase* phases, int n_phases, camp_mech** out);
 
+/* Compile a mechanism from its JSON description (paper Sect. 2.3: run-time configuration of
+ * species, phases and processes without recompiling). `text` is a NUL-terminated UTF-8 JSON
+ * document: {"species": [...], "phases": [...], "aerosol representation": {"instances":
+ * {phase: count}}, "processes": [...]}; the keys of every element and process type are
+ * listed at the top of csrc/mech_json.cpp. Names are resolved to ids, then camp_mech_load
+ * runs. Errors: CAMP_EINVAL with the offending element in camp_last_error (malformed JSON,
+ * unknown species, phase or type, missing parameters, or any camp_mech_load validation). */
+int camp_mech_load_json(const char* text, camp_mech** out);
+
+/* Serialize a compiled mechanism (every table the engines read) into one buffer, so other
+ * processes or ranks load it without the host compile (paper Sect. 2.1: the core object is
+ * packed on one process and unpacked on others). With buf NULL only *size (bytes needed) is
+ * written; else capacity must be at least that (CAMP_EINVAL otherwise). Host memory. */
+int camp_mech_pack(const camp_mech* mech, void* buf, size_t capacity, size_t* size);
+
+/* Rebuild a mechanism from camp_mech_pack's buffer (same library format version). The
+ * buffer is checked for magic, version, length and checksum and its tables for internal
+ * consistency; a buffer from any other source is rejected with CAMP_EINVAL. The caller may
+ * free buf on return. Device tables upload on first use, as for camp_mech_load. */
+int camp_mech_unpack(const void* buf, size_t size, camp_mech** out);
+
 typedef struct {
   int n_state;          /* N: state values per cell                                  */
   int n_gas;

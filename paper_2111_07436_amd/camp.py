@@ -90,6 +90,9 @@ _sig = {
     "camp_mech_load": (C.c_int, [C.POINTER(Reaction), C.c_int, C.POINTER(Species), C.c_int,
                                  C.POINTER(Phase), C.c_int, C.POINTER(_P)]),
     "camp_mech_info": (C.c_int, [_P, C.POINTER(MechInfo)]),
+    "camp_mech_load_json": (C.c_int, [C.c_char_p, C.POINTER(_P)]),
+    "camp_mech_pack": (C.c_int, [_P, _P, C.c_size_t, C.POINTER(C.c_size_t)]),
+    "camp_mech_unpack": (C.c_int, [_P, C.c_size_t, C.POINTER(_P)]),
     "camp_mech_export": (C.c_int, [_P, _P, _P, _P, _P]),
     "camp_mech_free": (None, [_P]),
     "camp_emulate_factor_solve": (C.c_int, [_P, C.c_int, C.c_int, _P, _P]),
@@ -169,7 +172,42 @@ def make_opts(engine="auto", max_order=0, max_steps=0, newton_max_iter=0, h_min=
 
 
 class Mech:
-    """A compiled mechanism (wraps camp_mech)."""
+    """A compiled mechanism (wraps camp_mech): from a workloads.Mechanism, or with
+    Mech.from_json / Mech.unpack."""
+
+    @classmethod
+    def _from_handle(cls, h, src=None):
+        self = cls.__new__(cls)
+        self.src = src
+        self._names, self._phase_ids = [], []
+        self.h = h
+        inf = MechInfo()
+        _check(_lib.camp_mech_info(h, C.byref(inf)))
+        self.info = inf.as_dict()
+        return self
+
+    @classmethod
+    def from_json(cls, text):
+        """camp_mech_load_json on a JSON document (str or bytes)."""
+        h = C.c_void_p()
+        _check(_lib.camp_mech_load_json(text.encode() if isinstance(text, str) else text, C.byref(h)))
+        return cls._from_handle(h)
+
+    @classmethod
+    def unpack(cls, data: bytes):
+        """camp_mech_unpack of a camp_mech_pack buffer."""
+        h = C.c_void_p()
+        buf = C.create_string_buffer(bytes(data), len(data))
+        _check(_lib.camp_mech_unpack(buf, len(data), C.byref(h)))
+        return cls._from_handle(h)
+
+    def pack(self) -> bytes:
+        """camp_mech_pack: the compiled mechanism as bytes."""
+        n = C.c_size_t(0)
+        _check(_lib.camp_mech_pack(self.h, None, 0, C.byref(n)))
+        buf = C.create_string_buffer(n.value)
+        _check(_lib.camp_mech_pack(self.h, buf, n.value, C.byref(n)))
+        return buf.raw[:n.value]
 
     def __init__(self, mech):
         self.src = mech

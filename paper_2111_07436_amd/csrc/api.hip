@@ -486,6 +486,67 @@ int camp_mech_load(const camp_reaction* rxns, int n_rxn, const camp_species* spe
   return CAMP_OK;
 }
 
+int camp_mech_load_json(const char* text, camp_mech** out) {
+  if (!out || !text) { set_error("NULL argument"); return CAMP_EINVAL; }
+  *out = nullptr;
+  MechDescription d;
+  std::string err;
+  try {
+    err = parse_mechanism_json(text, std::strlen(text), d);
+  } catch (const std::bad_alloc&) {
+    set_error("out of host memory");
+    return CAMP_ENOMEM;
+  }
+  if (!err.empty()) { set_error(err); return CAMP_EINVAL; }
+  std::vector<camp_species> sp(d.species.size());
+  for (size_t i = 0; i < sp.size(); ++i)
+    sp[i] = camp_species{d.species[i].name.c_str(), d.species[i].phase, d.species[i].mw,
+                         d.species[i].diff, d.species[i].accom};
+  std::vector<camp_phase> ph(d.phases.size());
+  for (size_t i = 0; i < ph.size(); ++i)
+    ph[i] = camp_phase{d.phases[i].name.c_str(), (int)d.phases[i].species.size(),
+                       d.phases[i].species.data(), d.phases[i].n_instances, d.phases[i].density,
+                       d.phases[i].mw_absorber};
+  return camp_mech_load(d.reactions.data(), (int)d.reactions.size(), sp.data(), (int)sp.size(),
+                        ph.data(), (int)ph.size(), out);
+}
+
+int camp_mech_pack(const camp_mech* mh, void* buf, size_t capacity, size_t* size) {
+  if (!mh || !size) { set_error("NULL argument"); return CAMP_EINVAL; }
+  std::vector<uint8_t> b;
+  try {
+    b = pack_compiled(mh->C, mh->stage);
+  } catch (const std::bad_alloc&) {
+    set_error("out of host memory");
+    return CAMP_ENOMEM;
+  }
+  *size = b.size();
+  if (!buf) return CAMP_OK;
+  if (capacity < b.size()) { set_error("buffer too small for the packed mechanism"); return CAMP_EINVAL; }
+  std::memcpy(buf, b.data(), b.size());
+  return CAMP_OK;
+}
+
+int camp_mech_unpack(const void* buf, size_t size, camp_mech** out) {
+  if (!out || !buf) { set_error("NULL argument"); return CAMP_EINVAL; }
+  *out = nullptr;
+  camp_mech* mh = new (std::nothrow) camp_mech();
+  if (!mh) { set_error("out of host memory"); return CAMP_ENOMEM; }
+  std::string err;
+  try {
+    err = unpack_compiled(static_cast<const uint8_t*>(buf), size, mh->C, mh->stage);
+  } catch (const std::bad_alloc&) {
+    err = "out of host memory";
+  }
+  if (!err.empty()) {
+    delete mh;
+    set_error(err);
+    return err == "out of host memory" ? CAMP_ENOMEM : CAMP_EINVAL;
+  }
+  *out = mh;
+  return CAMP_OK;
+}
+
 int camp_mech_info(const camp_mech* mh, camp_mech_info_t* info) {
   if (!mh || !info) { set_error("NULL argument"); return CAMP_EINVAL; }
   const Compiled& C = mh->C;

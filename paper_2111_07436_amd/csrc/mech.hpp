@@ -180,6 +180,30 @@ StageBlock build_stage_block(const Compiled& C, int wave_lists, bool use_tail);
 // x[N] (elimination order) in place. Returns false if a pivot is zero or not finite.
 bool emulate_factor_solve(const Compiled& C, const StageBlock& sb, double* m, double* x);
 
+// A mechanism description read from JSON (see mech_json.cpp): the arrays camp_mech_load takes.
+struct MechDescription {
+  struct Species {
+    std::string name;
+    int phase = -1;
+    double mw = 0.1, diff = 1e-5, accom = 0.1;
+  };
+  struct Phase {
+    std::string name;
+    std::vector<int> species;
+    int n_instances = 1;
+    double density = 1000.0, mw_absorber = 0.2;
+  };
+  std::vector<Species> species;
+  std::vector<Phase> phases;
+  std::vector<camp_reaction> reactions;
+};
+// Empty string on success, else the error (with the offending element).
+std::string parse_mechanism_json(const char* text, size_t len, MechDescription& out);
+
+// Packed compiled mechanism (see mech_pack.cpp); stage points to the four table blocks.
+std::vector<uint8_t> pack_compiled(const Compiled& C, const StageBlock* stage);
+std::string unpack_compiled(const uint8_t* buf, size_t size, Compiled& C, StageBlock* stage);
+
 // Returns an empty string on success, else the validation/compile error.
 std::string compile_mechanism(const camp_reaction* rxns, int n_rxn, const camp_species* sp,
                               int n_sp, const camp_phase* ph, int n_ph, Compiled& out);

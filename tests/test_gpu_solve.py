@@ -85,6 +85,20 @@ def test_rate_type_zoo(torch, engine):
     assert_parity(y[sample], yr, what=f"zoo/{engine}")
 
 
+def test_json_and_unpacked_mechanisms_solve_identically(torch):
+    """A mechanism read from its JSON description and one unpacked from camp_mech_pack give
+    the same states, bit for bit, as the mechanism given as arrays."""
+    from paper_2111_07436_amd import camp
+    from paper_2111_07436_amd import mechanism_json as MJ
+    wl = W.make_workload("zoo", n_cells=100)
+    a = camp.Mech(wl.mech)
+    ref = gpu_solve(a, wl, "wave")
+    for label, m in (("json", camp.Mech.from_json(MJ.to_json(wl.mech))),
+                     ("unpacked", camp.Mech.unpack(a.pack()))):
+        log(f"zoo {label}")
+        assert np.array_equal(gpu_solve(m, wl, "wave"), ref), label
+
+
 def test_c2_full_size_sampled(torch):
     """All 10,000 cells of the realistic gas config in the benchmark's launch configuration."""
     from paper_2111_07436_amd import camp
