@@ -69,9 +69,14 @@ enum {
  *                       p = {H298 [M Pa^-1], C [K]}; H(T) = H298 exp(C (1/T - 1/298)).
  *                       Condensation k_c = 4 pi r D_g f_FS(Kn, alpha) N (Fuchs-Sutugin);
  *                       evaporation k_c / (H 1000 V R T).
- *  SIMPOL_TRANSFER      as HENRY_TRANSFER; p = {B1, B2, B3, B4}, log10 p0[atm] =
+ *  SIMPOL_TRANSFER      as HENRY_TRANSFER; p = {B1, B2, B3, B4, raoult}, log10 p0[atm] =
  *                       B1/T + B2 + B3 T + B4 ln T; evaporation k_c p0 101325 / (R T n_abs),
- *                       n_abs = mass / mw_absorber of the instance.
+ *                       n_abs = mass / mw_absorber of the instance. raoult = 1 takes the
+ *                       full Raoult mole fraction instead (a Parameter, Sect. 2.2.2): the
+ *                       evaporation rate is k_c p0 101325 / (R T) * y_A / n_tot with
+ *                       n_tot = n_abs + the sum of every condensed species of the instance
+ *                       (a state-dependent amount, whose derivative enters the Jacobian);
+ *                       0 when n_tot = 0. raoult must be 0 or 1.
  *  TROE                 gas fall-off reaction: k = k0[M] / (1 + k0[M]/kinf)
  *                       Fc^(1 / (1 + (1/N) log10(k0[M]/kinf)^2)), with k0 and kinf of
  *                       Arrhenius form A exp(-Ea/(kb T)) (T/300)^B and [M] = P / (kb T) the
@@ -388,8 +393,13 @@ int camp_count_failed(int n_cells, const int* d_cell_status, int* n_failed, void
  *     the device; each request's cells are solved exactly as by camp_solve_device. --- */
 typedef struct camp_server camp_server;
 
-/* max_bytes: budget of device memory for in-flight requests (0 = 50% of free memory).
- * max_inflight: concurrent requests (streams), 1..64. */
+/* max_bytes: budget of device memory for in-flight requests (0 = 50% of free memory). A
+ * request's footprint is its own arrays (state, environment, status) plus the scratch of
+ * the launch chosen for it (the lane engines' per-call slabs or the wavefront engine's
+ * stream workspace); autotuning a cold (mechanism, size) bucket reserves the trials'
+ * scratch while they run. A request larger than the budget runs alone.
+ * max_inflight: concurrent requests (streams), 1..64. One server thread admits requests
+ * in FIFO order (tuning and launching outside the server's lock) and retires them. */
 int camp_serve_create(long long max_bytes, int max_inflight, camp_server** out);
 
 /* Submit a request on device-resident data (pointers stay owned by the caller and must
@@ -409,8 +419,8 @@ int camp_serve_poll(camp_server* srv, long long ticket, int* done, int* n_failed
 /* Block until the request completes. */
 int camp_serve_wait(camp_server* srv, long long ticket);
 
-/* Admit queued requests whose footprint now fits and retire finished ones; returns the
- * number of requests in flight in *inflight and queued in *queued. */
+/* Number of requests in flight (launched or being admitted) in *inflight and waiting in
+ * the FIFO in *queued. Never blocks on the device. */
 int camp_serve_progress(camp_server* srv, int* inflight, int* queued);
 
 void camp_serve_destroy(camp_server* srv);

@@ -4,7 +4,9 @@ A Process that acts on an aerosol phase is applied identically to every instance
 phase (Sect. 2.2.3 and Sect. 2.4.2: the Process operates on each instance as determined
 by the aerosol scheme). Gas-phase Processes apply once. Phase transfer
 (HenrysLawPhaseTransfer, SimpolPhaseTransfer) becomes, per instance, a condensation
-reaction G -> A and an evaporation reaction A -> G; an AqueousReversible reaction becomes,
+reaction G -> A and an evaporation reaction A -> G (SIMPOL with the full Raoult mole
+fraction adds a third, reaction-less entry carrying the instance's absorber amount, and its
+evaporation rate is divided by the instance's total condensed moles, a Parameter); an AqueousReversible reaction becomes,
 per instance, the forward reaction and the reverse one (products -> reactants, a repeated
 reactant returning as a product of that multiplicity).
 
@@ -21,6 +23,7 @@ TROE, CUSTOM_H2O2, CUSTOM_OH_HNO3, TUNNELING, AQ_REVERSIBLE = 8, 9, 10, 11, 12
 K_ARRHENIUS, K_PHOTOLYSIS, K_EMISSION, K_LOSS, K_CONDENSED = 1, 2, 3, 4, 5
 K_HENRY_COND, K_HENRY_EVAP, K_SIMPOL_COND, K_SIMPOL_EVAP = 6, 7, 8, 9
 K_TROE, K_H2O2, K_OHHNO3, K_TUNNEL, K_AQREV_FWD, K_AQREV_REV = 10, 11, 12, 13, 14, 15
+K_SIMPOL_EVAP_RAOULT, K_ABSORBER = 16, 17
 GAS_SPECIAL = {TROE: K_TROE, CUSTOM_H2O2: K_H2O2, CUSTOM_OH_HNO3: K_OHHNO3, TUNNELING: K_TUNNEL}
 
 
@@ -33,6 +36,10 @@ class XReaction:
     prod: List[int]
     yields: List[float]
     ext: int = -1      # index among externally-settable reactions, else -1
+    # Parameter (Sect. 2.2.2): the rate is divided by p = k[param_const] + sum of y over
+    # param_species (a diagnosed total amount), so J gains dr/dp dp/dy; -1: no parameter
+    param_const: int = -1
+    param_species: List[int] = None
 
 
 @dataclass
@@ -102,12 +109,19 @@ def expand(mech) -> Expanded:
         elif t in (HENRY, SIMPOL):
             p = r.phase
             gas = gas_state[r.react[0]]
+            raoult = t == SIMPOL and len(r.p) > 4 and r.p[4] != 0.0
             kc, ke = (K_HENRY_COND, K_HENRY_EVAP) if t == HENRY else (K_SIMPOL_COND, K_SIMPOL_EVAP)
             for i in range(mech.phases[p].n_instances):
                 g = first_inst[p] + i
                 aer = cond_index(p, i, r.prod[0])
                 rxns.append(XReaction(kc, ri, g, [gas], [aer], [1.0]))
-                rxns.append(XReaction(ke, ri, g, [aer], [gas], [1.0]))
+                if not raoult:
+                    rxns.append(XReaction(ke, ri, g, [aer], [gas], [1.0]))
+                    continue
+                block = [cond_index(p, i, s) for s in mech.phases[p].species]
+                rxns.append(XReaction(K_SIMPOL_EVAP_RAOULT, ri, g, [aer], [gas], [1.0],
+                                      param_const=len(rxns) + 1, param_species=block))
+                rxns.append(XReaction(K_ABSORBER, ri, g, [], [], []))
         else:
             raise ValueError(f"unknown reaction type {t}")
     return Expanded(n_state, n_gas, gas_state, inst_base, inst_phase, rxns)

@@ -9,6 +9,12 @@ occurrence and adds ``yield`` units of each product. Hence
     f = S r,        S[i, k] = sum(yields of i in k) - (occurrences of i among reactants of k)
     J = S (dr/dy),  dr_k/dy_j = k_k * sum over occurrences o of j of prod_{o' != o} y_{j_o'}
 
+A reaction may also depend on a Parameter (Sect. 2.2.2, a property diagnosed from the
+state): the full Raoult evaporation divides its rate by the instance's total condensed
+amount p = c + sum_{j in S} y_j, so r = k prod(y) / p, and by the chain rule
+dr/dy_j = (d mass-action term / dy_j) / p - r / p for j in S (dp/dy_j = 1). A p of exactly 0
+(an instance without absorber or condensed species) gives r = 0.
+
 Both are computed densely; the arithmetic works for complex y so that the Jacobian can
 be checked by the complex-step derivative.
 """
@@ -41,11 +47,21 @@ class DenseSystem:
                     ii.append(i); jj.append(j); kk.append(k); oo.append(o); cc.append(S[i, k])
         self.jc = (np.array(ii, dtype=np.int64), np.array(jj, dtype=np.int64),
                    np.array(kk, dtype=np.int64), np.array(oo, dtype=np.int64), np.array(cc))
+        self.params = [(k, xr.param_const, list(xr.param_species), np.nonzero(S[:, k])[0])
+                       for k, xr in enumerate(x.rxns) if xr.param_const >= 0]
+
+    def factors(self, k, y):
+        """Per-reaction parameter factor 1/p (1 for reactions without a parameter)."""
+        phi = np.ones(len(k), dtype=np.result_type(y, k))
+        for kk, d, spec, _ in self.params:
+            p = k[d] + sum(y[j] for j in spec)
+            phi[kk] = 0.0 if p == 0 else 1.0 / p
+        return phi
 
     def rates(self, k, y):
         ye = np.append(y, 1.0)
         g = ye[self.react]                            # [R, 3]
-        return k * g[:, 0] * g[:, 1] * g[:, 2]
+        return k * g[:, 0] * g[:, 1] * g[:, 2] * self.factors(k, y)
 
     def f(self, k, y):
         return self.S @ self.rates(k, y)
@@ -56,7 +72,15 @@ class DenseSystem:
         g = ye[self.react]
         # occurrence o: derivative of g0*g1*g2 w.r.t. g_o is the product of the other two
         others = np.stack([g[:, 1] * g[:, 2], g[:, 0] * g[:, 2], g[:, 0] * g[:, 1]], axis=1)
+        phi = self.factors(k, y)
         ii, jj, kk, oo, cc = self.jc
         J = np.zeros((n, n), dtype=np.result_type(y, k))
-        np.add.at(J, (ii, jj), cc * k[kk] * others[kk, oo])
+        np.add.at(J, (ii, jj), cc * (k * phi)[kk] * others[kk, oo])
+        # chain rule through the parameter: dr/dp dp/dy_j = -r phi for every j in its set
+        if self.params:
+            r = self.rates(k, y)
+            for kk_, d, spec, members in self.params:
+                for i in members:
+                    for j in spec:
+                        J[i, j] += self.S[i, kk_] * (-r[kk_] * phi[kk_])
         return J

@@ -24,7 +24,10 @@ State concentrations are mol m^-3 of air. Formulas (Table of Process classes):
   k_evap = k_c / (H 1000 V R T).
   SIMPOL.1: log10 p0[atm] = B1/T + B2 + B3 T + B4 ln T; with Raoult's law over a fixed
   absorbing amount n_abs = m / MW_abs, G_eq = (A / n_abs) p0 101325 / (R T), so
-  k_evap = k_c p0 101325 / (R T n_abs).
+  k_evap = k_c p0 101325 / (R T n_abs). With the full Raoult mole fraction (p[4] != 0) the
+  amount absorbing is n_abs plus every condensed species of the instance: the evaporation
+  rate is k_c p0 101325 / (R T) A / n_tot, its rate constant k_c p0 101325 / (R T), and the
+  instance's absorber amount n_abs is carried by a reaction-less entry.
 * Troe fall-off: k = k0[M] / (1 + k0[M]/kinf) Fc^E with E = 1 / (1 + (1/N) log10(k0[M]/kinf)^2);
   CustomH2o2: k = k1 + k2[M]; CustomOhHno3: k = k0 + k3[M] / (1 + k3[M]/k2); every k_i of
   the Arrhenius form with D = 300 K and E = 0, [M] the number density of air (molecule
@@ -42,7 +45,8 @@ import numpy as np
 
 from .expand import (K_ARRHENIUS, K_PHOTOLYSIS, K_EMISSION, K_LOSS, K_CONDENSED,
                      K_HENRY_COND, K_HENRY_EVAP, K_SIMPOL_COND, K_SIMPOL_EVAP,
-                     K_TROE, K_H2O2, K_OHHNO3, K_TUNNEL, K_AQREV_FWD, K_AQREV_REV)
+                     K_TROE, K_H2O2, K_OHHNO3, K_TUNNEL, K_AQREV_FWD, K_AQREV_REV,
+                     K_SIMPOL_EVAP_RAOULT, K_ABSORBER)
 
 AVOGADRO = 6.02214076e23          # mol^-1
 BOLTZMANN = 1.380649e-23          # J K^-1
@@ -154,6 +158,9 @@ def rate_constants_cell(mech, x, T, P, cos_sza, radius, mass, override=None):
                 continue
             rad = radius[g]
             volume = m / ph.density
+            if xr.kind == K_ABSORBER:
+                k[n] = m / ph.mw_absorber
+                continue
             if xr.kind in (K_AQREV_FWD, K_AQREV_REV):
                 kk = p[2]
                 if xr.kind == K_AQREV_FWD:
@@ -178,6 +185,9 @@ def rate_constants_cell(mech, x, T, P, cos_sza, radius, mass, override=None):
                 n_abs = m / ph.mw_absorber
                 p0 = simpol_p0_atm(p[0], p[1], p[2], p[3], T)
                 k[n] = kc * p0 * ATM_PA / (GAS_CONSTANT * T * n_abs)
+            elif xr.kind == K_SIMPOL_EVAP_RAOULT:
+                p0 = simpol_p0_atm(p[0], p[1], p[2], p[3], T)
+                k[n] = kc * p0 * ATM_PA / (GAS_CONSTANT * T)
             else:
                 raise ValueError(xr.kind)
     return k

@@ -5,7 +5,8 @@ solver can use a sparse Jacobian (Table of Process functions, get_used_jacobian_
 and the linear solver is a sparse direct LU (Sect. 2.4.1, KLU). Here:
 
 * ``structural_pattern``: (i, j) is used when species j is a reactant of some expanded
-  reaction in which species i takes part (as reactant or product); the diagonal is always
+  reaction in which species i takes part (as reactant or product), or j is one of the
+  species a reaction's Parameter is diagnosed from (Sect. 2.2.2); the diagonal is always
   included (the Newton matrix is I - gamma J).
 * ``symbolic_fill``: plain boolean Gaussian elimination in a given pivot order: eliminating
   pivot k makes (i, j) nonzero for every i after k with (i, k) nonzero and every j after k
@@ -21,7 +22,7 @@ def structural_pattern(x):
     P = np.eye(n, dtype=bool)
     for xr in x.rxns:
         members = set(xr.react) | set(xr.prod)
-        for j in set(xr.react):
+        for j in set(xr.react) | set(xr.param_species or []):
             for i in members:
                 P[i, j] = True
     return P

@@ -436,6 +436,12 @@ class DeviceEnv:
     def c_env(self):
         return Env(*[None if t is None else t.data_ptr() for t in self.t])
 
+    def head(self, n):
+        """The first n cells, sharing this environment's device memory."""
+        v = DeviceEnv.__new__(DeviceEnv)
+        v.t = [None if t is None else t[:n] for t in self.t]
+        return v
+
 
 class Server:
     """Continuous-batching request server (wraps camp_server)."""

@@ -62,6 +62,8 @@ int upload(camp_mech* mh, int device, DeviceTables& out) {
          o_nr = add(nr.data(), 4 * R), o_v = add(v.data(), 8 * v.size()),
          o_react = add(C.rx_react.data(), 4 * C.rx_react.size()),
          o_pofs = add(C.rx_pofs.data(), 4 * C.rx_pofs.size()),
+         o_rptr = add(C.raoult_ptr.data(), 4 * C.raoult_ptr.size()),
+         o_rao = add(C.raoult.data(), 4 * C.raoult.size()),
          o_tptr = add(C.term_ptr.data(), 4 * C.term_ptr.size()),
          o_trxn = add(C.term_rxn.data(), 4 * C.term_rxn.size()),
          o_tcoef = add(C.term_coef.data(), 8 * C.term_coef.size()),
@@ -110,6 +112,9 @@ int upload(camp_mech* mh, int device, DeviceTables& out) {
   d.rs_v = (const double*)(b + o_v);
   d.rx_react = (const int*)(b + o_react);
   d.rx_pofs = (const int*)(b + o_pofs);
+  d.raoult_ptr = (const int*)(b + o_rptr);
+  d.raoult = (const int*)(b + o_rao);
+  d.n_raoult = (int)C.raoult_ptr.size() - 1;
   d.term_ptr = (const int*)(b + o_tptr);
   d.term_rxn = (const int*)(b + o_trxn);
   d.term_coef = (const double*)(b + o_tcoef);
@@ -278,7 +283,7 @@ int wave_launch_shape(const DevMech& dm, const Tuning& tu, int n_cells, bool has
   WaveShape w;
   w.lanes = tu.lanes;
   w.waves = tu.lanes == 64 ? std::max(1, tu.waves) : 1;
-  w.stage = std::max(0, std::min(4, tu.stage));
+  w.stage = wave_effective_mode(dm, std::max(0, std::min(4, tu.stage)));
   if (wave_wg_lds_bytes(dm, w.waves, w.stage, tu.lanes) > kLdsBytes) {
     set_error("mechanism does not fit the wavefront engine's LDS budget");
     return CAMP_EINVAL;
@@ -348,6 +353,19 @@ int stream_workspace(camp_mech* mh, hipStream_t stream, size_t bytes, char** out
   return CAMP_OK;
 }
 
+namespace {
+int fused_lane_slots() { return std::max(256, n_cus() * 4 * 64 * 2); }
+}  // namespace
+
+size_t solve_scratch_bytes(const DevMech& dm, const Tuning& tu, int n_cells, bool has_order) {
+  if (n_cells <= 0) return 0;
+  if (tu.engine == CAMP_ENGINE_PLAIN) return lane_scratch_bytes(dm, n_cells, 0);
+  if (tu.engine == CAMP_ENGINE_FUSED_LANE) return lane_scratch_bytes(dm, n_cells, fused_lane_slots());
+  WaveShape w;
+  if (wave_launch_shape(dm, tu, n_cells, has_order, &w) != CAMP_OK) return 0;
+  return w.bytes ? std::max(w.bytes, (size_t)1 << 20) : 0;
+}
+
 // Dispatch of one device solve with a resolved tuning.
 int solve_device_tuned(camp_mech* mh, const DevMech& dm, int n_cells, double* d_state,
                        const camp_env* d_env, const SolveParams& sp, const camp_opts* opts,
@@ -358,8 +376,7 @@ int solve_device_tuned(camp_mech* mh, const DevMech& dm, int n_cells, double* d_
   if (tu.engine == CAMP_ENGINE_PLAIN) {
     e = run_plain(dm, env, d_state, n_cells, sp, d_status, d_stats, use_graph, stream);
   } else if (tu.engine == CAMP_ENGINE_FUSED_LANE) {
-    const int slots = std::max(256, n_cus() * 4 * 64 * 2);
-    e = run_fused_lane(dm, env, d_state, n_cells, sp, d_status, d_stats, slots, stream);
+    e = run_fused_lane(dm, env, d_state, n_cells, sp, d_status, d_stats, fused_lane_slots(), stream);
   } else {
     const int* order = opts ? opts->cell_order : nullptr;
     WaveShape w;

@@ -24,9 +24,6 @@
 namespace camp {
 
 Tuning default_tuning(const DevMech& dm, int n_cells);
-int solve_device_tuned(camp_mech* mh, const DevMech& dm, int n_cells, double* d_state,
-                       const camp_env* d_env, const SolveParams& sp, const camp_opts* opts,
-                       int* d_status, camp_cell_stats* d_stats, hipStream_t stream, const Tuning& tu);
 
 namespace {
 
@@ -112,6 +109,8 @@ std::vector<Tuning> candidates(const DevMech& dm) {
     for (int lanes : {64, 128, 256}) {
       if (!wave_lanes_ok(dm.N, lanes) || !dm.sv[lanes / 128].base) continue;
       for (int stage : {2, 1, 0, 4, 3}) {
+        // mechanisms with Parameters run every launch in one mode (see wave_effective_mode)
+        if (wave_effective_mode(dm, stage) != stage && stage != 3) continue;
         const int wmax = wave_max_waves(dm.N, stage, lanes);
         const int cap = wave_resident_cells_per_cu(dm.N, stage, lanes);
         Tuning best;
@@ -168,6 +167,17 @@ bool cached_tuning(camp_mech* mh, const DevMech& dm, int n_cells, const SolvePar
   return true;
 }
 
+namespace {
+// Trial sizes: enough cells for several per resident slot, and four times that for the
+// throughput round of a large call.
+int trial_cells(int n_cells) { return std::min(n_cells, std::max(4096, n_cus_dev() * 64)); }
+}  // namespace
+
+size_t autotune_scratch_bytes(const DevMech& dm, int n_cells) {
+  const int big = std::min(n_cells, 4 * trial_cells(n_cells));
+  return 2 * sizeof(double) * (size_t)big * dm.N + 4 * (size_t)big + 256;
+}
+
 int autotuned(camp_mech* mh, const DevMech& dm, int n_cells, double* d_state,
               const camp_env* d_env, const SolveParams& sp, const camp_opts* opts,
               hipStream_t stream, Tuning* out) {
@@ -196,12 +206,11 @@ int autotuned(camp_mech* mh, const DevMech& dm, int n_cells, double* d_state,
   // slot. Then, for a larger call, the three fastest launches run again on four times as
   // many cells: near the trial size the lowest per-cell latency wins (the last cells finish
   // alone), while a large call is decided by throughput.
-  const int cus = n_cus_dev();
-  const int trial = std::min(n_cells, std::max(4096, cus * 64));
+  const int trial = trial_cells(n_cells);
   const int big = std::min(n_cells, 4 * trial);
   const size_t sbytes = sizeof(double) * (size_t)big * dm.N;
   char* buf = nullptr;
-  hipError_t e = hipMallocAsync((void**)&buf, 2 * sbytes + 4 * (size_t)big + 256, stream);
+  hipError_t e = hipMallocAsync((void**)&buf, autotune_scratch_bytes(dm, n_cells), stream);
   if (e != hipSuccess) return hip_fail(e, "hipMallocAsync(autotune)");
   double* src = reinterpret_cast<double*>(buf);
   double* work = reinterpret_cast<double*>(buf + sbytes);

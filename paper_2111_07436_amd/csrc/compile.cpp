@@ -343,6 +343,9 @@ std::string compile_mechanism(const camp_reaction* rxns, int n_rxn, const camp_s
     int nr, np;
     int react[3], prod[3];
     double yld[3];
+    // Parameter (full Raoult): the rate is divided by kc[pconst] + sum of y over pspec
+    int pconst = -1;
+    std::vector<int> pspec;
   };
   std::vector<X> xs;
   std::vector<RateSpec> rs;
@@ -590,10 +593,20 @@ std::string compile_mechanism(const camp_reaction* rxns, int n_rxn, const camp_s
         return err.str();
       }
       const bool henry = t == CAMP_RXN_HENRY_TRANSFER;
+      const bool raoult = !henry && q.p[4] != 0.0;
+      if (!henry && q.p[4] != 0.0 && q.p[4] != 1.0) {
+        err << "reaction " << r << ": SIMPOL full-Raoult flag p[4] must be 0 or 1";
+        return err.str();
+      }
+      if (raoult && !(ph[p].mw_absorber_kg_mol > 0)) {
+        err << "reaction " << r << ": full-Raoult SIMPOL needs a positive absorber molecular weight";
+        return err.str();
+      }
       for (int i = 0; i < ph[p].n_instances; ++i) {
         for (int dir = 0; dir < 2; ++dir) {
           RateSpec s = base_spec(henry ? (dir == 0 ? KR_HENRY_COND : KR_HENRY_EVAP)
-                                       : (dir == 0 ? KR_SIMPOL_COND : KR_SIMPOL_EVAP));
+                                       : (dir == 0 ? KR_SIMPOL_COND
+                                                   : (raoult ? KR_SIMPOL_EVAP_RAOULT : KR_SIMPOL_EVAP)));
           s.inst = phase_first_inst[p] + i;
           s.v[0] = g.diff_m2_s;
           s.v[1] = g.mw_kg_mol;
@@ -609,6 +622,23 @@ std::string compile_mechanism(const camp_reaction* rxns, int n_rxn, const camp_s
           x.react[0] = dir == 0 ? gs : as;
           x.prod[0] = dir == 0 ? as : gs;
           x.yld[0] = 1.0;
+          if (raoult && dir == 1) {
+            // total condensed amount of the instance: the absorber entry pushed next plus
+            // every species of the phase
+            x.pconst = (int)xs.size() + 1;
+            for (int m = 0; m < ph[p].n_species; ++m)
+              x.pspec.push_back(cond_state(p, i, ph[p].species[m]));
+          }
+          xs.push_back(x);
+          rs.push_back(s);
+        }
+        if (raoult) {
+          RateSpec s = base_spec(KR_ABSORBER);
+          s.inst = phase_first_inst[p] + i;
+          s.v[3] = ph[p].density_kg_m3;
+          s.v[4] = ph[p].mw_absorber_kg_mol;
+          s.nr = 0;
+          X x{};
           xs.push_back(x);
           rs.push_back(s);
         }
@@ -642,6 +672,8 @@ std::string compile_mechanism(const camp_reaction* rxns, int n_rxn, const camp_s
     members[k] = m;
     for (int o = 0; o < x.nr; ++o)
       for (auto& e : m) edges.push_back({e.first, x.react[o]});   // (row i, col j)
+    for (int j : x.pspec)
+      for (auto& e : m) edges.push_back({e.first, j});
   }
   for (int i = 0; i < N; ++i) edges.push_back({i, i});
 
@@ -658,7 +690,7 @@ std::string compile_mechanism(const camp_reaction* rxns, int n_rxn, const camp_s
     long long nnz = 0, n_part = 0;
     for (int i = 0; i < N; ++i)
       for (int j = 0; j < N; ++j) nnz += F.get(i, j);
-    for (const X& x : xs) n_part += x.nr;
+    for (const X& x : xs) n_part += x.nr + (x.pconst >= 0 ? 1 : 0);
     // Gauss-Jordan keeps 4K doubles in the partials / rates scratch of a cell
     const int scratch_k = (int)(std::max<long long>(n_part, (long long)xs.size()) / 4);
     C.nnz_lu = (int)nnz;
@@ -695,9 +727,19 @@ std::string compile_mechanism(const camp_reaction* rxns, int n_rxn, const camp_s
   for (int k = 0; k < R; ++k) {
     C.rx_nr[k] = xs[k].nr;
     for (int o = 0; o < xs[k].nr; ++o) C.rx_react[3 * k + o] = C.iperm[xs[k].react[o]];
-    C.rx_pofs[k + 1] = C.rx_pofs[k] + xs[k].nr;
+    // a reaction with a parameter has one more partial: dr/dp dp/dy_j, equal for every j
+    C.rx_pofs[k + 1] = C.rx_pofs[k] + xs[k].nr + (xs[k].pconst >= 0 ? 1 : 0);
   }
   C.n_partials = C.rx_pofs[R];
+  C.raoult_ptr.assign(1, 0);
+  C.raoult.clear();
+  for (int k = 0; k < R; ++k) {
+    if (xs[k].pconst < 0) continue;
+    C.raoult.push_back(k);
+    C.raoult.push_back(xs[k].pconst);
+    for (int j : xs[k].pspec) C.raoult.push_back(C.iperm[j]);
+    C.raoult_ptr.push_back((int)C.raoult.size());
+  }
 
   // forcing terms by species (elimination position), reactions ascending
   {
@@ -724,6 +766,14 @@ std::string compile_mechanism(const camp_reaction* rxns, int n_rxn, const camp_s
           if (e.second == 0.0) continue;
           int s = slot(C.iperm[e.first], j);
           by[s].push_back({C.rx_pofs[k] + o, e.second});
+        }
+      }
+    for (int k = 0; k < R; ++k)
+      for (int jj : xs[k].pspec) {
+        int j = C.iperm[jj];
+        for (auto& e : members[k]) {
+          if (e.second == 0.0) continue;
+          by[slot(C.iperm[e.first], j)].push_back({C.rx_pofs[k] + xs[k].nr, e.second});
         }
       }
     C.jc_ptr.assign(C.nnz + 1, 0);

@@ -43,6 +43,10 @@ struct DevMech {
   // reactions
   const int* rx_react;         // [R * 3], -1 padded, elimination positions
   const int* rx_pofs;          // [R + 1]
+  // reactions with a Parameter (full Raoult): records {k, d, s_1 .. s_m}, see Compiled
+  const int* raoult_ptr;       // [n_raoult + 1]
+  const int* raoult;
+  int n_raoult;
   // forcing terms per species
   const int* term_ptr;
   const int* term_rxn;
@@ -158,6 +162,7 @@ __device__ inline double rate_constant(const DevMech& m, int r, double T, double
   const int g = m.rs_inst[r];
   const double ms = mass[g];
   if (ms == 0.0) return 0.0;
+  if (kind == 17) return ms / v[4];  // absorbing moles of the instance
   if (kind == 14 || kind == 15) {  // aqueous reversible: forward K k_r, reverse k_r, on molarities
     const int nr = m.rs_nr[r];
     const double vol = ms / v[3];
@@ -190,10 +195,25 @@ __device__ inline double rate_constant(const DevMech& m, int r, double T, double
     const double H = v[5] * exp(v[6] * (1.0 / T - 1.0 / 298.0));
     return kc / (H * 1000.0 * (ms / rho) * kGasConstant * T);
   }
-  // SIMPOL evaporation
+  // SIMPOL evaporation; with the full Raoult mole fraction (kind 16) the rate's parameter
+  // divides by the instance's total condensed moles instead of n_abs
   const double p0 = exp10(v[5] / T + v[6] + v[7] * T + v[8] * log(T));
+  if (kind == 16) return kc * p0 * kAtmPa / (kGasConstant * T);
   const double n_abs = ms / v[4];
   return kc * p0 * kAtmPa / (kGasConstant * T * n_abs);
+}
+
+// Factor 1/p of parameter record q (reaction k = its first entry): p = kc(d) plus the sum of
+// the state over the record's species, summed in record order; 0 when p = 0 (an instance
+// with neither absorber nor condensed mass).
+template <class Kc, class Y>
+__device__ __forceinline__ double parameter_factor(const DevMech& m, int q, int& k, Kc kc, Y y) {
+  const int b = m.raoult_ptr[q], e = m.raoult_ptr[q + 1];
+  k = m.raoult[b];
+  double s = 0.0;
+  for (int i = b + 2; i < e; ++i) s += y(m.raoult[i]);
+  const double p = kc(m.raoult[b + 1]) + s;
+  return p != 0.0 ? 1.0 / p : 0.0;
 }
 
 // Moves a double between lanes with one DPP pattern (both 32-bit halves).

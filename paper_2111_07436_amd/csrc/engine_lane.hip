@@ -74,6 +74,12 @@ struct Lane {
       if (c >= 0) r *= y(c);
       P(k) = r;
     }
+    for (int q = 0; q < m.n_raoult; ++q) {   // rates with a parameter: r = kc prod(y) / p
+      int k;
+      const double phi = parameter_factor(m, q, k, [&](int d) { return kc(d); },
+                                          [&](int j) { return y(j); });
+      P(k) *= phi;
+    }
     int ok = 1;
     for (int t = 0; t < m.N; ++t) {
       double acc = 0.0;
@@ -94,6 +100,15 @@ struct Lane {
       if (a >= 0) P(base) = kk * yb * yc;
       if (b >= 0) P(base + 1) = kk * ya * yc;
       if (cc >= 0) P(base + 2) = kk * ya * yb;
+    }
+    for (int q = 0; q < m.n_raoult; ++q) {   // chain rule through the parameter p
+      int k;
+      const double phi = parameter_factor(m, q, k, [&](int d) { return kc(d); },
+                                          [&](int j) { return y(j); });
+      const int o = m.rx_pofs[k];
+      const double r = kc(k) * y(m.rx_react[3 * k]) * phi;
+      P(o) = kc(k) * phi;
+      P(o + 1) = -r * phi;
     }
     for (int s = 0; s < m.Z; ++s) {
       double acc = 0.0;
@@ -699,6 +714,23 @@ struct LaneLayout {
   }
 };
 
+}  // namespace
+
+namespace {
+// Cell slots of a launch: one per cell for the plain engine (n_slots == 0), else the fused
+// engine's resident slots, at most one per cell.
+size_t lane_slots(int n_cells, int n_slots) {
+  return n_slots == 0 ? align_up((size_t)n_cells, kWave)
+                      : align_up((size_t)(n_slots < n_cells ? n_slots : n_cells), 256);
+}
+}  // namespace
+
+size_t lane_scratch_bytes(const DevMech& m, int n_cells, int n_slots) {
+  return n_cells > 0 ? LaneLayout(m, lane_slots(n_cells, n_slots)).bytes : 0;
+}
+
+namespace {
+
 void bind(LaneCtx& C, char* base, const LaneLayout& L) {
   auto D = [&](size_t o) { return reinterpret_cast<double*>(base + o); };
   auto I = [&](size_t o) { return reinterpret_cast<int*>(base + o); };
@@ -745,7 +777,7 @@ hipError_t run_plain(const DevMech& m, const DevEnv& env, double* state, int n_c
                      const SolveParams& sp, int* status, camp_cell_stats* stats, int use_graph,
                      hipStream_t stream) {
   if (n_cells <= 0) return hipSuccess;
-  const size_t slots = align_up((size_t)n_cells, kWave);
+  const size_t slots = lane_slots(n_cells, 0);
   LaneLayout lay(m, slots);
   char* base = nullptr;
   hipError_t e = hipMallocAsync((void**)&base, lay.bytes, stream);
@@ -828,7 +860,7 @@ hipError_t run_fused_lane(const DevMech& m, const DevEnv& env, double* state, in
                           const SolveParams& sp, int* status, camp_cell_stats* stats, int n_slots,
                           hipStream_t stream) {
   if (n_cells <= 0) return hipSuccess;
-  size_t slots = align_up((size_t)(n_slots < n_cells ? n_slots : n_cells), 256);
+  size_t slots = lane_slots(n_cells, n_slots);
   LaneLayout lay(m, slots);
   char* base = nullptr;
   hipError_t e = hipMallocAsync((void**)&base, lay.bytes, stream);

@@ -26,6 +26,8 @@ int wave_resident_cells_per_cu(int n_state, int mode, int lanes) {
   return 4 * per_simd / (lanes / 64);
 }
 
+int wave_effective_mode(const DevMech& m, int mode) { return m.n_raoult ? kParamMode : mode; }
+
 size_t wave_cell_bytes(const DevMech& m) { return sizeof(double) * cell_doubles(m, 0); }
 
 size_t wave_lds_bytes(const DevMech& m) { return wave_cell_bytes(m); }
@@ -33,6 +35,7 @@ size_t wave_lds_bytes(const DevMech& m) { return wave_cell_bytes(m); }
 // LDS bytes of a workgroup of `waves` cells in launch mode `mode` (0..4), with `lanes` per
 // cell (which picks the table layout).
 size_t wave_wg_lds_bytes(const DevMech& m, int waves, int mode, int lanes) {
+  mode = wave_effective_mode(m, mode);
   return (size_t)staged_bytes(m.sv[lanes / 128], mode) +
          (size_t)waves * sizeof(double) * cell_doubles(m, mode);
 }
@@ -42,7 +45,9 @@ hipError_t launch_bdf_wave(const DevMech& m, const DevEnv& env, double* state, i
                            double* kc_glob, int grid, int waves, int stage, int lanes,
                            bool attr_only, hipStream_t stream) {
   if (!wave_lanes_ok(m.N, lanes)) return hipErrorInvalidValue;
-  if (stage < 0 || stage > 4) return hipErrorInvalidValue;
+  if (stage < 0 || (stage > 4 && stage != kParamMode)) return hipErrorInvalidValue;
+  stage = wave_effective_mode(m, stage);
+  if (stage == kParamMode && !m.n_raoult) return hipErrorInvalidValue;
   const StageView& view = m.sv[lanes / 128];
   if (!view.base || view.wave_lists != lanes / kWave) return hipErrorInvalidValue;
   if (waves < 1 || waves > wave_max_waves(m.N, stage, lanes)) return hipErrorInvalidValue;
@@ -64,7 +69,7 @@ namespace {
 // One wavefront per cell; the same device code as the fused engine (tables read from
 // global memory), on row-major [cells][...] arrays in user state order.
 
-template <int NPL>
+template <int NPL, bool kPar>
 __global__ __launch_bounds__(kWave) void wave_step_kernel(DevMech m, int op, int n_cells,
                                                           const double* kin, const double* yin,
                                                           double* out, double gamma) {
@@ -74,8 +79,8 @@ __global__ __launch_bounds__(kWave) void wave_step_kernel(DevMech m, int op, int
   double* yl = lds + m.Z;
   double* xl = yl + m.N;
   double* P = xl + m.N;
-  const WaveCell<NPL, kWave> W{m, Tabs{g, g, m.sv[3]}, lds, yl, xl, P, P + np + 8, P + np,
-                               (int)threadIdx.x};
+  const WaveCell<NPL, kWave, kPar> W{m, Tabs{g, g, m.sv[3]}, lds, yl, xl, P, P + np + 8, P + np,
+                                     (int)threadIdx.x};
   const int cell = blockIdx.x;
   if (cell >= n_cells) return;
   const int lane = threadIdx.x;
@@ -157,11 +162,16 @@ hipError_t launch_wave_step(const DevMech& m, int op, int n_cells, const double*
   if (n_cells == 0) return hipSuccess;
 #define CAMP_STEP_CASE(K)                                                                      \
   case K: {                                                                                    \
-    hipError_t e = hipFuncSetAttribute((const void*)wave_step_kernel<K>,                       \
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);   \
+    const void* fn = m.n_raoult ? (const void*)wave_step_kernel<K, true>                       \
+                                : (const void*)wave_step_kernel<K, false>;                     \
+    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds); \
     if (e != hipSuccess) return e;                                                             \
-    hipLaunchKernelGGL(wave_step_kernel<K>, dim3(n_cells), dim3(kWave), lds, stream, m, op,     \
-                       n_cells, kin, yin, out, gamma);                                         \
+    if (m.n_raoult)                                                                            \
+      hipLaunchKernelGGL((wave_step_kernel<K, true>), dim3(n_cells), dim3(kWave), lds, stream, \
+                         m, op, n_cells, kin, yin, out, gamma);                                \
+    else                                                                                       \
+      hipLaunchKernelGGL((wave_step_kernel<K, false>), dim3(n_cells), dim3(kWave), lds, stream, \
+                         m, op, n_cells, kin, yin, out, gamma);                                \
     return hipGetLastError();                                                                  \
   }
   switch (npl) {

@@ -282,7 +282,7 @@ struct Tabs {
   __device__ int tl_rs(int i) const { return reinterpret_cast<const uint16_t*>(b + v.so_tail_rs)[i]; }
 };
 
-template <int NPL, int G>
+template <int NPL, int G, bool kPar = false>
 struct WaveCell {
   // Terms per lane issued together in the LU and sweep levels: levels of large mechanisms
   // hold several terms per lane, small ones rarely more than one.
@@ -368,6 +368,15 @@ struct WaveCell {
                   [&](const TermEntry& t, const double (&y)[3]) {
                     P[t.x] = t.c * yfac(t.e, 0, y[0]) * yfac(t.e, 1, y[1]) * yfac(t.e, 2, y[2]);
                   });
+    if constexpr (kPar) {   // rates with a parameter: r = kc prod(y) / p
+      sync();
+      for (int q = lane; q < m.n_raoult; q += G) {
+        int k;
+        const double phi = parameter_factor(m, q, k, [&](int d) { return kc[d]; },
+                                            [&](int j) { return yl[j]; });
+        P[k] *= phi;
+      }
+    }
     for (int t = lane; t < m.N; t += G) xl[t] = 0.0;
     sync();
     for_terms_split<kTermBatch, kWave>(
@@ -399,6 +408,18 @@ struct WaveCell {
                   });
     for (int s = lane; s < m.Z; s += G) M[s] = 0.0;
     sync();
+    if constexpr (kPar) {   // chain rule through the parameter p: kc / p and -r / p
+      for (int q = lane; q < m.n_raoult; q += G) {
+        int k;
+        const double phi = parameter_factor(m, q, k, [&](int d) { return kc[d]; },
+                                            [&](int j) { return yl[j]; });
+        const int o = m.rx_pofs[k];
+        const double r = kc[k] * yl[m.rx_react[3 * k]] * phi;
+        P[o] = kc[k] * phi;
+        P[o + 1] = -r * phi;
+      }
+      sync();
+    }
     const double mc = -c;
     for_terms_split<kTermBatch, kWave>(
         uniform(tb.jt_lp(wid())), uniform(tb.jt_lp(wid() + 1)), wlane(),
@@ -715,9 +736,9 @@ __device__ __forceinline__ void rescale_hist(double (&D)[kHist][NPL], int q, dou
 // LDS; `bad` flags a non-finite rate constant on this lane). full != 0: full Newton, with a
 // fresh Jacobian and LU at every iteration; else Newton with Jacobian reuse. On success
 // the state row is overwritten; on failure it is left as it was.
-template <int NPL, int G>
+template <int NPL, int G, bool kPar>
 __device__ __forceinline__ int integrate(const DevMech& m, double* yrow, const SolveParams& sp, int bad, int full,
-                         camp_cell_stats& cs, const WaveCell<NPL, G>& W) {
+                         camp_cell_stats& cs, const WaveCell<NPL, G, kPar>& W) {
   const int lane = W.lane;
   const int N = m.N;
   int status = ST_OK;
@@ -1035,10 +1056,10 @@ __device__ __forceinline__ int integrate(const DevMech& m, double* yrow, const S
 // Rate constants, then the integration; a cell whose integration fails (too many steps,
 // step below the minimum, repeated error-test or Newton failures) is integrated again from
 // its input: with full Newton, then with full Newton and a tighter absolute tolerance.
-template <int NPL, int G>
+template <int NPL, int G, bool kPar>
 __device__ __forceinline__ void solve_one_cell(const DevMech& m, const DevEnv& env, double* state, int cell,
                                const SolveParams& sp, int* status_out, camp_cell_stats* stats_out,
-                               const WaveCell<NPL, G>& W) {
+                               const WaveCell<NPL, G, kPar>& W) {
   const int lane = W.lane;
   camp_cell_stats cs = {0, 0, 0, 0, 0, 0, 0, 0};
   const double Tk = env.T[cell], Pp = env.P[cell];
@@ -1058,7 +1079,7 @@ __device__ __forceinline__ void solve_one_cell(const DevMech& m, const DevEnv& e
   for (int attempt = sp.full_newton ? 1 : 0; attempt < kAttempts; ++attempt) {
     SolveParams spa = sp;
     if (attempt == 2) spa.atol *= kRetryAtolFactor;
-    status = integrate<NPL, G>(m, yrow, spa, bad, attempt > 0, cs, W);
+    status = integrate(m, yrow, spa, bad, attempt > 0, cs, W);
     if (status < ST_MAX_STEPS || status > ST_NEWTON_FAIL) break;
   }
   if (lane == 0) {
@@ -1075,10 +1096,16 @@ __device__ __forceinline__ void solve_one_cell(const DevMech& m, const DevEnv& e
 //   3  tables from global memory and rate constants in a global per-wavefront scratch
 //      (persistent launches only), for mechanisms whose per-cell LDS is the occupancy limit
 //   4  core index tables staged in LDS and rate constants in the global scratch
+//   5  as 3, for mechanisms with Parameters (rates divided by a state-dependent amount):
+//      the only mode such mechanisms run in, so the kernels of the other modes carry no
+//      parameter code
 // In modes 3 and 4, cells of at most two species per lane (up to 128 state variables on one
 // wavefront, up to 256 on two) run a kernel built for three wavefronts per SIMD (at most 168
 // registers): up to 12 one-wavefront cells per workgroup, or six two-wavefront cells per CU.
-__host__ __device__ constexpr bool kc_global(int mode) { return mode >= 3; }
+constexpr int kParamMode = 5;
+// The table staging of a launch mode (mode 5 stages as mode 3).
+__host__ __device__ constexpr int table_mode(int mode) { return mode == kParamMode ? 3 : mode; }
+__host__ __device__ constexpr bool kc_global(int mode) { return table_mode(mode) >= 3; }
 
 // LDS doubles of one cell: M [Z], y [N], x [N], partials/rates, 8 doubles of group
 // scratch, and the rate constants unless they live in global scratch (modes 3, 4).
@@ -1089,6 +1116,7 @@ __host__ __device__ inline size_t cell_doubles(const DevMech& m, int mode) {
 
 // Bytes of the table block staged in LDS in launch mode `mode`.
 __host__ __device__ inline int staged_bytes(const StageView& v, int mode) {
+  mode = table_mode(mode);
   return mode == 2 ? v.bytes : (mode == 1 || mode == 4) ? v.core_bytes : 0;
 }
 
@@ -1096,14 +1124,14 @@ __host__ __device__ inline int staged_bytes(const StageView& v, int mode) {
 template <int kStage>
 __device__ __forceinline__ Tabs stage_tables(const StageView& v, double* lds) {
   const char* g = reinterpret_cast<const char*>(v.base);
-  if (kStage == 0 || kStage == 3) return Tabs{g, g, v};
+  if (table_mode(kStage) == 0 || table_mode(kStage) == 3) return Tabs{g, g, v};
   const uint4* src = reinterpret_cast<const uint4*>(v.base);
   uint4* dst = reinterpret_cast<uint4*>(lds);
   const int n16 = staged_bytes(v, kStage) / 16;
   for (int i = threadIdx.x; i < n16; i += blockDim.x) dst[i] = src[i];
   __syncthreads();
   const char* l = reinterpret_cast<const char*>(lds);
-  return Tabs{l, kStage == 2 ? l : g, v};
+  return Tabs{l, table_mode(kStage) == 2 ? l : g, v};
 }
 
 
@@ -1147,10 +1175,10 @@ __global__ __launch_bounds__((max_threads<NPL, kStage, G>()),
   double* P = xl + m.N;
   double* red = P + np;
   double* kc = kc_global(kStage) ? kc_glob + (size_t)(blockIdx.x * W + wid) * m.R : red + 8;
-  const WaveCell<NPL, G> Wc{m, tab, base, yl, xl, P, kc, red, lane};
+  const WaveCell<NPL, G, kStage == kParamMode> Wc{m, tab, base, yl, xl, P, kc, red, lane};
   if (!queue) {
     const int cell = blockIdx.x * W + wid;
-    if (cell < n_cells) solve_one_cell<NPL, G>(m, env, state, cell, sp, status, stats, Wc);
+    if (cell < n_cells) solve_one_cell(m, env, state, cell, sp, status, stats, Wc);
     return;
   }
   while (true) {
@@ -1167,7 +1195,7 @@ __global__ __launch_bounds__((max_threads<NPL, kStage, G>()),
     }
     if (cell >= n_cells) break;
     if (sp.order && *sp.order_bad == 0) cell = sp.order[cell];
-    solve_one_cell<NPL, G>(m, env, state, cell, sp, status, stats, Wc);
+    solve_one_cell(m, env, state, cell, sp, status, stats, Wc);
   }
 }
 
@@ -1193,6 +1221,7 @@ hipError_t run_wave(const WaveParams& p, int stage) {
     case 2: return launch_wave_npl<NPL, 2, G>(p.m, p.env, p.state, p.n_cells, p.sp, p.status, p.stats, p.queue, p.kc_glob, p.grid, p.waves, p.lds, p.attr_only, p.stream);
     case 3: return launch_wave_npl<NPL, 3, G>(p.m, p.env, p.state, p.n_cells, p.sp, p.status, p.stats, p.queue, p.kc_glob, p.grid, p.waves, p.lds, p.attr_only, p.stream);
     case 4: return launch_wave_npl<NPL, 4, G>(p.m, p.env, p.state, p.n_cells, p.sp, p.status, p.stats, p.queue, p.kc_glob, p.grid, p.waves, p.lds, p.attr_only, p.stream);
+    case kParamMode: return launch_wave_npl<NPL, kParamMode, G>(p.m, p.env, p.state, p.n_cells, p.sp, p.status, p.stats, p.queue, p.kc_glob, p.grid, p.waves, p.lds, p.attr_only, p.stream);
     default: return hipErrorInvalidValue;
   }
 }

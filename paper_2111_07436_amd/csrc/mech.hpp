@@ -27,7 +27,9 @@ enum RateKind : int {
   KR_OHHNO3 = 12,
   KR_TUNNEL = 13,
   KR_AQREV_FWD = 14,
-  KR_AQREV_REV = 15
+  KR_AQREV_REV = 15,
+  KR_SIMPOL_EVAP_RAOULT = 16,
+  KR_ABSORBER = 17
 };
 
 constexpr int kRateParams = 12;
@@ -42,6 +44,10 @@ constexpr int kRateParams = 12;
 //   TROE, H2O2, OHHNO3, TUNNEL: v[0..8] = the process parameters p[0..8], v[9] = the unit
 //                  factor (N_A 1e-6)^(n_r-1) from molecule cm^-3 to mol m^-3
 //   AQREV_FWD/REV: v = {A, C, k_r, density}
+//   SIMPOL_EVAP_RAOULT: as *_EVAP; its rate constant omits the absorber amount, which the
+//                  rate's parameter supplies (the instance's total condensed moles)
+//   ABSORBER  : v[3] = density, v[4] = mw_absorber; no reactants or products, rate
+//                  constant m / mw_absorber (the absorbing moles of one phase instance)
 struct RateSpec {
   int kind;
   int ext;    // column of rate_override, or -1
@@ -80,6 +86,12 @@ struct Compiled {
   std::vector<int> rx_nr;               // [R]
   std::vector<int> rx_pofs;             // [R + 1] partial offsets
   int n_partials = 0;
+  // Reactions with a Parameter (Sect. 2.2.2): record q in [raoult_ptr[q], raoult_ptr[q+1])
+  // of `raoult` holds {k, d, s_1 .. s_m}: reaction k's rate is divided by
+  // p = kc[d] + y[s_1] + .. + y[s_m] (elimination positions), with r = 0 when p = 0. Its
+  // partials are P[rx_pofs[k]] = kc[k] / p (the reactant occurrence) and
+  // P[rx_pofs[k] + 1] = -r / p (the chain rule through p, shared by every s_j).
+  std::vector<int> raoult_ptr{0}, raoult;
 
   // forcing: f_t = sum_q term_coef[q] * r[term_rxn[q]], q in [term_ptr[t], term_ptr[t+1])
   std::vector<int> term_ptr, term_rxn;

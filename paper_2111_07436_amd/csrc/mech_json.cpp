@@ -22,7 +22,8 @@
 //   PHOTOLYSIS: "J0 [s-1]", "scale by cos(sza)" (false); EMISSION: "rate [mol m-3 s-1]";
 //   FIRST_ORDER_LOSS: "rate constant [s-1]"
 //   HENRYS_LAW_PHASE_TRANSFER: "phase", "gas species", "aerosol species", "H298 [M Pa-1]", "C [K]"
-//   SIMPOL_PHASE_TRANSFER: "phase", "gas species", "aerosol species", "B" ([B1, B2, B3, B4])
+//   SIMPOL_PHASE_TRANSFER: "phase", "gas species", "aerosol species", "B" ([B1, B2, B3, B4]),
+//     "full Raoult" (false: the fixed absorber amount only)
 //   TROE: "k0" and "kinf" ({"A", "Ea/kb [K]", "B"}), "Fc" (0.6), "N" (1.0)
 //   CUSTOM_H2O2: "k1", "k2"; CUSTOM_OH_HNO3: "k0", "k2", "k3" (each {"A", "Ea/kb [K]", "B"})
 //   WENNBERG_TUNNELING: "A", "B [K]", "C [K3]"
@@ -356,6 +357,7 @@ std::string parse_mechanism_json(const char* text, size_t len, MechDescription& 
           ok = b->arr[k].kind == JVal::NUM;
           if (ok) p[k] = b->arr[k].num;
         }
+        ok = ok && number(q, "full Raoult", 0.0, &p[4]);
         break;
       }
       case CAMP_RXN_TROE:

@@ -58,6 +58,9 @@ size_t wave_cell_bytes(const DevMech& m);
 size_t wave_wg_lds_bytes(const DevMech& m, int waves, int stage, int lanes);
 int wave_max_waves(int n_state, int mode, int lanes);
 int wave_lanes_ok(int n_state, int lanes);
+// The launch mode a wavefront launch of mechanism m in mode `mode` (0..4) runs in: the
+// parameter mode (as mode 3, with the Parameter passes) for mechanisms with Parameters.
+int wave_effective_mode(const DevMech& m, int mode);
 int wave_resident_cells_per_cu(int n_state, int mode, int lanes);
 // attr_only: set the kernel's launch attributes (LDS size) and return without launching.
 hipError_t launch_bdf_wave(const DevMech& m, const DevEnv& env, double* state, int n_cells,
@@ -76,6 +79,9 @@ hipError_t run_fused_lane(const DevMech& m, const DevEnv& env, double* state, in
                           const SolveParams& sp, int* status, camp_cell_stats* stats,
                           int n_slots, hipStream_t stream);
 hipError_t launch_count_failed(int n, const int* status, int* out, hipStream_t stream);
+// Device scratch one lane-engine call allocates (for the call's duration): n_slots = 0 for
+// the plain engine, else the fused engine's slot count.
+size_t lane_scratch_bytes(const DevMech& m, int n_cells, int n_slots);
 hipError_t launch_fill_int(int* p, int n, int v, hipStream_t stream);
 // Zeroes seen[0..n) and raises *bad (not cleared here) unless order[0..n) is a permutation.
 hipError_t launch_check_order(const int* order, int n, int* seen, int* bad, hipStream_t stream);
@@ -92,6 +98,15 @@ int resolve_tuning(camp_mech* mh, const DevMech& dm, int n_cells, double* d_stat
                    hipStream_t stream, bool run_trials, Tuning* out);
 bool cached_tuning(camp_mech* mh, const DevMech& dm, int n_cells, const SolveParams& sp,
                    Tuning* out);
+// Device bytes the autotuner's trials allocate for a call of n_cells (freed when it returns).
+size_t autotune_scratch_bytes(const DevMech& dm, int n_cells);
+// Device bytes a solve with tuning `tu` uses beyond its inputs and outputs: the lane
+// engines' per-call slabs, or the fused wavefront launch's stream workspace (cached per
+// mechanism and stream, at least 1 MiB once allocated).
+size_t solve_scratch_bytes(const DevMech& dm, const Tuning& tu, int n_cells, bool has_order);
+int solve_device_tuned(camp_mech* mh, const DevMech& dm, int n_cells, double* d_state,
+                       const camp_env* d_env, const SolveParams& sp, const camp_opts* opts,
+                       int* d_status, camp_cell_stats* d_stats, hipStream_t stream, const Tuning& tu);
 int wave_launch_shape(const DevMech& dm, const Tuning& tu, int n_cells, bool has_order,
                       WaveShape* out);
 hipError_t enqueue_wave(const DevMech& dm, const DevEnv& env, double* d_state, int n_cells,

@@ -1,12 +1,16 @@
 // Request server: continuous batching of solve requests on one device.
 //
 // A request names a resident mechanism and device-resident state/environment of any cell
-// count. Requests wait in a FIFO until their device-memory footprint fits the budget and a
-// stream slot is free; each admitted request is enqueued on its own HIP stream as one
-// fused-engine solve (a persistent kernel that pulls the request's cells from its queue),
-// so several requests' kernels are resident together and the hardware dispatcher fills
-// CUs freed by one request with workgroups of another. A progress thread retires finished
-// requests (event query), reads their failed-cell counts and admits waiting ones.
+// count. Requests wait in a FIFO; one admission thread takes them in order: it resolves the
+// request's launch (autotuning a cold (mechanism, size) bucket, with the trials' scratch
+// reserved against the budget while they run), computes the request's device footprint for
+// that launch, waits until the footprint fits the budget and a stream slot is free, and
+// enqueues the solve on the slot's HIP stream. Tuning and launching happen outside the
+// server lock, so submit / poll / progress never wait on a launch. Each admitted request is
+// one fused-engine solve (a persistent kernel that pulls the request's cells from its
+// queue), so several requests' kernels are resident together and the hardware dispatcher
+// fills CUs freed by one request with workgroups of another. The same thread retires
+// finished requests (event query) and reads their failed-cell counts.
 // Each cell is solved exactly as by camp_solve_device: no arithmetic crosses cells or
 // requests, so a request's result does not depend on what else is in flight.
 #include <hip/hip_runtime.h>
@@ -38,7 +42,7 @@ struct Request {
   camp_opts opts;
   bool has_opts;
   int* d_status;
-  size_t footprint;
+  size_t footprint = 0;
   Clock::time_point t_submit, t_done;
   int slot = -1;
   bool done = false;
@@ -55,12 +59,14 @@ struct camp_server {
   int n_slots = 0;
   std::vector<hipStream_t> streams;
   std::vector<hipEvent_t> events;
-  std::vector<long long> slot_ticket;   // 0: free
+  std::vector<long long> slot_ticket;   // 0: free; > 0: request in flight; < 0: held by
+                                        // the admission thread (trials or an enqueue)
   int* pinned = nullptr;                // [n_slots] failed counts
   int* d_counts = nullptr;              // [n_slots] device failed counts
   std::mutex mu;
-  std::condition_variable cv;
+  std::condition_variable cv;           // a request finished
   std::deque<long long> pending;
+  long long admitting = 0;              // ticket taken from the FIFO, not yet launched
   std::map<long long, Request> reqs;
   long long next_ticket = 1;
   std::atomic<bool> stop{false};
@@ -69,25 +75,19 @@ struct camp_server {
 
 namespace {
 
-// Device bytes a request occupies while in flight: its resident arrays plus the engine's
-// scratch (the lane engines carry per-cell slabs; the wavefront engine only a counter).
-size_t footprint(const camp_mech* mh, int n_cells, const camp_opts* o) {
+// Bytes of a request's own device arrays (state, environment, status).
+size_t array_bytes(const camp_mech* mh, int n_cells) {
   const Compiled& C = mh->C;
-  size_t per_cell = 8 * ((size_t)C.n_state + 3 + 2 * (size_t)C.n_inst + C.n_ext) + 4;
-  size_t bytes = per_cell * (size_t)n_cells + 4096;
-  const int engine = o ? o->engine : CAMP_ENGINE_AUTO;
-  if (engine == CAMP_ENGINE_PLAIN || engine == CAMP_ENGINE_FUSED_LANE) {
-    const size_t np = std::max<size_t>(C.n_partials, C.n_rxn);
-    bytes += 8 * ((size_t)C.n_rxn + np + C.nnz + 14 * (size_t)C.n_state + 16) * (size_t)n_cells;
-  }
-  return bytes;
+  const size_t per_cell = 8 * ((size_t)C.n_state + 3 + 2 * (size_t)C.n_inst + C.n_ext) + 4;
+  return per_cell * (size_t)n_cells;
 }
 
-// Retire finished requests and admit waiting ones. Caller holds srv->mu.
-void pump_locked(camp_server* srv) {
+// Retire finished requests. Caller holds srv->mu. Returns whether any finished.
+bool retire_locked(camp_server* srv) {
+  bool any = false;
   for (int s = 0; s < srv->n_slots; ++s) {
     const long long t = srv->slot_ticket[s];
-    if (!t) continue;
+    if (t <= 0) continue;
     if (hipEventQuery(srv->events[s]) != hipSuccess) continue;
     Request& r = srv->reqs[t];
     r.done = true;
@@ -95,45 +95,136 @@ void pump_locked(camp_server* srv) {
     r.n_failed = srv->pinned[s];
     srv->in_use -= (long long)r.footprint;
     srv->slot_ticket[s] = 0;
+    any = true;
   }
-  while (!srv->pending.empty()) {
-    Request& r = srv->reqs[srv->pending.front()];
+  return any;
+}
+
+// Blocks (retiring finished requests meanwhile) until `bytes` fit the budget, or nothing is
+// in flight (a lone request always runs), and, with want_slot, a stream slot is free; then
+// reserves the bytes. Returns the slot (or 0 without want_slot), -1 when stopping.
+int reserve(camp_server* srv, size_t bytes, bool want_slot) {
+  while (!srv->stop.load()) {
+    bool finished;
     int slot = -1;
-    for (int s = 0; s < srv->n_slots; ++s)
-      if (!srv->slot_ticket[s]) {
-        slot = s;
-        break;
+    {
+      std::lock_guard<std::mutex> g(srv->mu);
+      finished = retire_locked(srv);
+      if (want_slot)
+        for (int s = 0; s < srv->n_slots && slot < 0; ++s)
+          if (!srv->slot_ticket[s]) slot = s;
+      const bool fits = srv->in_use + (long long)bytes <= srv->budget || srv->in_use == 0;
+      if (fits && (slot >= 0 || !want_slot)) {
+        srv->in_use += (long long)bytes;
+        return want_slot ? slot : 0;
       }
-    const bool fits = srv->in_use + (long long)r.footprint <= srv->budget ||
-                      srv->in_use == 0;   // a lone request always runs
-    if (slot < 0 || !fits) break;
-    srv->pending.pop_front();
-    hipStream_t st = srv->streams[slot];
-    r.slot = slot;
-    r.rc = camp_solve_device(r.mech, r.n_cells, r.d_state, &r.env, r.dt, r.rtol, r.atol,
-                             r.has_opts ? &r.opts : nullptr, r.d_status, nullptr, st);
-    if (r.rc == CAMP_OK) {
-      launch_count_failed(r.n_cells, r.d_status, srv->d_counts + slot, st);
-      hipMemcpyAsync(srv->pinned + slot, srv->d_counts + slot, sizeof(int), hipMemcpyDeviceToHost, st);
-      hipEventRecord(srv->events[slot], st);
-      srv->slot_ticket[slot] = r.ticket;
-      srv->in_use += (long long)r.footprint;
-    } else {
-      r.done = true;
-      r.t_done = Clock::now();
-      r.n_failed = r.n_cells;
     }
+    if (finished) srv->cv.notify_all();
+    std::this_thread::sleep_for(std::chrono::microseconds(50));
   }
+  return -1;
+}
+
+void finish_failed(camp_server* srv, Request& r, int rc) {
+  {
+    std::lock_guard<std::mutex> g(srv->mu);
+    r.rc = rc;
+    r.done = true;
+    r.t_done = Clock::now();
+    r.n_failed = r.n_cells;
+    srv->admitting = 0;
+  }
+  srv->cv.notify_all();
+}
+
+// Resolve, size and launch the request at the head of the FIFO.
+void admit(camp_server* srv, Request& r) {
+  camp_mech* mh = r.mech;
+  const camp_opts* opts = r.has_opts ? &r.opts : nullptr;
+  int rc = check_solve_args(mh, r.n_cells, r.d_state, &r.env, r.dt, r.rtol, r.atol);
+  const DevMech* dm = nullptr;
+  if (rc == CAMP_OK) rc = resident(mh, &dm);
+  if (rc != CAMP_OK) return finish_failed(srv, r, rc);
+  const SolveParams sp = make_params(r.dt, r.rtol, r.atol, opts);
+  const size_t arrays = array_bytes(mh, r.n_cells);
+  Tuning tu;
+  const bool forced = opts && opts->engine != CAMP_ENGINE_AUTO;
+  if (r.n_cells > 0 && !forced && !cached_tuning(mh, *dm, r.n_cells, sp, &tu)) {
+    // cold bucket: the trials run on a free slot's stream, with their scratch (and the
+    // request's arrays) reserved against the budget while they run
+    const size_t trial = arrays + autotune_scratch_bytes(*dm, r.n_cells);
+    const int slot = reserve(srv, trial, true);
+    if (slot < 0) return finish_failed(srv, r, CAMP_EINVAL);
+    {
+      std::lock_guard<std::mutex> g(srv->mu);
+      srv->slot_ticket[slot] = -r.ticket;   // held by the trials
+    }
+    rc = resolve_tuning(mh, *dm, r.n_cells, r.d_state, &r.env, sp, opts, srv->streams[slot], true, &tu);
+    {
+      std::lock_guard<std::mutex> g(srv->mu);
+      srv->slot_ticket[slot] = 0;
+      srv->in_use -= (long long)trial;
+    }
+    if (rc != CAMP_OK) return finish_failed(srv, r, rc);
+  } else if (r.n_cells > 0) {
+    rc = resolve_tuning(mh, *dm, r.n_cells, r.d_state, &r.env, sp, opts, nullptr, false, &tu);
+    if (rc != CAMP_OK) return finish_failed(srv, r, rc);
+  }
+  r.footprint = arrays + (r.n_cells > 0 ? solve_scratch_bytes(*dm, tu, r.n_cells,
+                                                              opts && opts->cell_order) : 0);
+  const int slot = reserve(srv, r.footprint, true);
+  if (slot < 0) return finish_failed(srv, r, CAMP_EINVAL);
+  hipStream_t st = srv->streams[slot];
+  r.slot = slot;
+  {
+    std::lock_guard<std::mutex> g(srv->mu);
+    srv->slot_ticket[slot] = -r.ticket;   // reserved while the launch is enqueued
+  }
+  rc = r.n_cells > 0 ? solve_device_tuned(mh, *dm, r.n_cells, r.d_state, &r.env, sp, opts,
+                                          r.d_status, nullptr, st, tu)
+                     : CAMP_OK;
+  hipError_t e = hipSuccess;
+  if (rc == CAMP_OK) {
+    e = launch_count_failed(r.n_cells, r.d_status, srv->d_counts + slot, st);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(srv->pinned + slot, srv->d_counts + slot, sizeof(int), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipEventRecord(srv->events[slot], st);
+    if (e != hipSuccess) rc = hip_fail(e, "server completion record");
+  }
+  if (rc != CAMP_OK) {
+    // nothing of this request is left in flight that the slot must wait for
+    hipStreamSynchronize(st);
+    {
+      std::lock_guard<std::mutex> g(srv->mu);
+      srv->slot_ticket[slot] = 0;
+      srv->in_use -= (long long)r.footprint;
+    }
+    return finish_failed(srv, r, rc);
+  }
+  std::lock_guard<std::mutex> g(srv->mu);
+  srv->slot_ticket[slot] = r.ticket;
+  srv->admitting = 0;
 }
 
 void worker_loop(camp_server* srv) {
   hipSetDevice(srv->device);
   while (!srv->stop.load()) {
+    Request* r = nullptr;
+    bool finished;
     {
       std::lock_guard<std::mutex> g(srv->mu);
-      pump_locked(srv);
+      finished = retire_locked(srv);
+      if (!srv->pending.empty()) {
+        srv->admitting = srv->pending.front();
+        srv->pending.pop_front();
+        r = &srv->reqs[srv->admitting];   // std::map: stable while other entries are added
+      }
     }
-    srv->cv.notify_all();
+    if (finished) srv->cv.notify_all();
+    if (r) {
+      admit(srv, *r);
+      continue;
+    }
     std::this_thread::sleep_for(std::chrono::microseconds(50));
   }
 }
@@ -201,12 +292,10 @@ int camp_serve_submit(camp_server* srv, camp_mech* mech, int n_cells, double* d_
   r.has_opts = opts != nullptr;
   if (opts) r.opts = *opts;
   r.d_status = d_cell_status;
-  r.footprint = footprint(mech, n_cells, opts);
   r.t_submit = Clock::now();
   srv->reqs[r.ticket] = r;
   srv->pending.push_back(r.ticket);
   *ticket = r.ticket;
-  pump_locked(srv);
   return CAMP_OK;
 }
 
@@ -250,9 +339,9 @@ int camp_serve_progress(camp_server* srv, int* inflight, int* queued) {
     return CAMP_EINVAL;
   }
   std::lock_guard<std::mutex> g(srv->mu);
-  pump_locked(srv);
   int n = 0;
-  for (long long t : srv->slot_ticket) n += t != 0;
+  for (long long t : srv->slot_ticket) n += t > 0;
+  if (srv->admitting) ++n;
   if (inflight) *inflight = n;
   if (queued) *queued = (int)srv->pending.size();
   return CAMP_OK;

@@ -62,6 +62,8 @@ def to_dict(mech: W.Mechanism) -> dict:
             e.update({"H298 [M Pa-1]": p[0], "C [K]": p[1]})
         elif t == W.RXN_SIMPOL_TRANSFER:
             e["B"] = p[:4]
+            if p[4]:
+                e["full Raoult"] = True
         elif t == W.RXN_TROE:
             e.update({"k0": _k(p, 0), "kinf": _k(p, 3), "Fc": p[6], "N": p[7]})
         elif t == W.RXN_CUSTOM_H2O2:

@@ -37,7 +37,7 @@ RXN_EMISSION = 3             # p = [E (mol m^-3 s^-1)]
 RXN_FIRST_ORDER_LOSS = 4     # p = [k (s^-1)]
 RXN_CONDENSED_ARRHENIUS = 5  # p = [A, Ea/kb (K), B, D (K), E (Pa^-1), aqueous_flag]
 RXN_HENRY_TRANSFER = 6       # p = [H298 (M Pa^-1), C (K)]
-RXN_SIMPOL_TRANSFER = 7      # p = [B1, B2, B3, B4]
+RXN_SIMPOL_TRANSFER = 7      # p = [B1, B2, B3, B4, full_raoult]
 RXN_TROE = 8                 # p = [A0, Ea0/kb, B0, Ainf, Eainf/kb, Binf, Fc, N]
 RXN_CUSTOM_H2O2 = 9          # p = [A1, Ea1/kb, B1, A2, Ea2/kb, B2]
 RXN_CUSTOM_OH_HNO3 = 10      # p = [A0, Ea0/kb, B0, A2, Ea2/kb, B2, A3, Ea3/kb, B3]
@@ -399,16 +399,21 @@ def gen_rate_type_zoo(rng) -> Mechanism:
     """A small mechanism with every process type: gas-phase Arrhenius, photolysis,
     emission, first-order loss, Troe fall-off, HO2 self-reaction, OH + HNO3, tunneling, and
     an aqueous phase of 3 instances with Henry's-law and SIMPOL transfer, condensed-phase
-    Arrhenius and reversible reactions. Parameters are drawn from ranges typical of
-    tropospheric kinetics (pre-exponential factors in molecule cm^-3 units)."""
+    Arrhenius and reversible reactions, and an organic phase of 2 instances whose SIMPOL
+    partitioning takes the full Raoult mole fraction (a state-dependent Parameter).
+    Parameters are drawn from ranges typical of tropospheric kinetics (pre-exponential
+    factors in molecule cm^-3 units)."""
     lu = lambda lo, hi: float(np.exp(rng.uniform(np.log(lo), np.log(hi))))
     g = [Species(name=f"Z{i}", phase=-1, mw=float(rng.uniform(0.03, 0.2)),
                  diff=float(rng.uniform(0.8e-5, 2.0e-5)), accom=float(rng.uniform(0.05, 0.5)))
          for i in range(12)]
     aq = [Species(name=f"AQ{i}", phase=0) for i in range(5)]
-    species = g + aq
+    org = [Species(name=f"ORG{i}", phase=1) for i in range(3)]
+    species = g + aq + org
     A0, A1, A2, A3, A4 = 12, 13, 14, 15, 16
-    phases = [Phase("aqueous", [A0, A1, A2, A3, A4], 3, density=1000.0, mw_absorber=0.1)]
+    O0, O1, O2 = 17, 18, 19
+    phases = [Phase("aqueous", [A0, A1, A2, A3, A4], 3, density=1000.0, mw_absorber=0.1),
+              Phase("organic", [O0, O1, O2], 2, density=1200.0, mw_absorber=0.25)]
 
     def arr3():
         return [lu(1e-13, 1e-11), float(rng.uniform(-600.0, 600.0)), float(rng.uniform(-1.5, 0.0))]
@@ -447,6 +452,15 @@ def gen_rate_type_zoo(rng) -> Mechanism:
         Reaction(RXN_AQUEOUS_REVERSIBLE, [A0], [A1], [1.0], [lu(0.5, 20.0), float(rng.uniform(-2000, 2000)), lu(1e-3, 1e-1), 0, 0, 0, 0, 0, 0, 0], phase=0),
         Reaction(RXN_AQUEOUS_REVERSIBLE, [A2, A2], [A3], [1.0], [lu(0.1, 10.0), float(rng.uniform(-2000, 2000)), lu(1e-3, 1e-1), 0, 0, 0, 0, 0, 0, 0], phase=0),
         Reaction(RXN_CONDENSED_ARRHENIUS, [A1, A3], [A4], [1.0], [lu(0.1, 10.0), 0, 0, 300, 0, 1.0], phase=0),
+    ]
+    # organic phase: two semi-volatile species absorbed by Raoult's law over the whole
+    # condensed amount, one converted to a nonvolatile product
+    rx += [
+        Reaction(RXN_SIMPOL_TRANSFER, [8], [O0], [1.0],
+                 [float(rng.uniform(3.0e3, 4.5e3)), float(rng.uniform(-21, -17)), 0, 0, 1.0, 0], phase=1),
+        Reaction(RXN_SIMPOL_TRANSFER, [10], [O1], [1.0],
+                 [float(rng.uniform(3.0e3, 4.5e3)), float(rng.uniform(-21, -17)), 0, 0, 1.0, 0], phase=1),
+        Reaction(RXN_CONDENSED_ARRHENIUS, [O0], [O2], [1.0], [lu(1e-5, 1e-3), 0, 0, 300, 0, 0.0], phase=1),
     ]
     return Mechanism(species=species, phases=phases, reactions=rx)
 

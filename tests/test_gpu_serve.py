@@ -97,3 +97,27 @@ def test_poisoned_request_fails_alone(torch):
     assert np.array_equal(yg.cpu().numpy(), solo[0])
     assert np.array_equal(yb.cpu().numpy(), bad["y0"].cpu().numpy())
     srv.close()
+
+
+def test_auto_engine_cold_cache_matches_solo(torch, monkeypatch):
+    # Fresh mechanisms: the server autotunes each cold (mechanism, size) bucket on its own
+    # thread; solo solves afterwards reuse the cached launch, so results agree bit for bit.
+    from paper_2111_07436_amd import camp
+    monkeypatch.delenv("CAMP_TUNE_CACHE", raising=False)
+    sizes = [5000, 300, 4000, 9000]
+    mechs, reqs = _requests(camp, torch, sizes)
+    srv = camp.Server(max_bytes=0, max_inflight=3)
+    outs = [(r["y0"].clone(), torch.full((r["n"],), -7, dtype=torch.int32, device="cuda")) for r in reqs]
+    torch.cuda.synchronize()
+    tickets = [srv.submit(r["m"], r["denv"], y, 3600.0, 1e-4, 1e-12, st, None)
+               for r, (y, st) in zip(reqs, outs)]
+    for t in tickets:
+        srv.wait(t)
+        assert srv.poll(t)[0]
+    torch.cuda.synchronize()
+    srv.close()
+    solo = _solo(camp, torch, reqs, None)
+    for (y, st), (ys, ss), r in zip(outs, solo, reqs):
+        assert np.array_equal(st.cpu().numpy(), ss)
+        assert np.array_equal(y.cpu().numpy(), ys), r["n"]
+        assert not np.any(ss), r["n"]
