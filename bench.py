@@ -509,6 +509,15 @@ def main():
         "fp64": {"achieved": tflops, "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
                  "frac": tflops / FP64_VECTOR_PEAK_TFLOPS, "flops_per_launch": flops},
     }
+    try:
+        copy_gbs, fma_tflops = camp.probe_copy(), camp.probe_fma()
+        out["roofline"]["measured_peaks"] = {
+            "hbm_copy_gbs": copy_gbs, "fp64_fma_tflops": fma_tflops,
+            "frac_of_copy": achieved / copy_gbs, "fp64_frac_of_fma": tflops / fma_tflops,
+            "how": "camp_probe_copy (2 GiB device copy, 16-byte nontemporal accesses, bytes read + written) and camp_probe_fma "
+                   "(16 independent FP64 FMA chains per lane, 4096 workgroups of 256)"}
+    except Exception as exc:   # a probe failure must not lose the measurement above
+        log(f"peak probes failed: {exc}")
     stored = None
     if not args.no_accuracy and name in EQUAL_ACCURACY_TOL:
         scells, sref, _ = stored_oracle(name)

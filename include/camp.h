@@ -293,6 +293,12 @@ typedef struct {
                         /* permutation, ignored (cells run in index order). Other        */
                         /* engines and non-persistent launches ignore it. Results never  */
                         /* depend on the order: each cell is integrated alone.           */
+  double lu_gamma_drift;/* Jacobian reuse: refactor when h / beta drifts from the value    */
+                        /* of the last factorization by more than this fraction          */
+                        /* (default 0.3; <= 0 = default)                                 */
+  int lu_max_age;       /* ... or after this many accepted steps (default 20)            */
+  double newton_tol;    /* Newton convergence: estimated remaining error in the weighted */
+                        /* norm at most this (default 0.1)                               */
 } camp_opts;
 
 /* Per-cell counters (optional output). */
@@ -388,6 +394,20 @@ int camp_lu_solve_device(camp_mech* mech, int n_cells, const double* d_lu, doubl
 
 /* Number of cells with nonzero status (device status array), written to *n_failed. */
 int camp_count_failed(int n_cells, const int* d_cell_status, int* n_failed, void* stream);
+
+/* --- Measurement probes: what the device sustains, as denominators beside the published
+ *     peaks of a roofline. Both synchronize on `stream` and return the rate. --- */
+
+/* Device copy d_dst[i] = d_src[i] of n doubles (n even, 16-byte aligned buffers owned by
+ * the caller), `reps` timed launches after one warm-up: *gb_per_s = 16 n reps / time
+ * (bytes read plus written). */
+int camp_probe_copy(const double* d_src, double* d_dst, size_t n, int reps, void* stream,
+                    double* gb_per_s);
+
+/* FP64 FMA rate: `blocks` workgroups of 256 threads, each thread 16 independent FMA chains
+ * of `iters` steps; d_sink (caller-owned, blocks * 256 doubles) receives the sums.
+ * *tflop_per_s = 2 * 16 * iters * blocks * 256 / time. */
+int camp_probe_fma(double* d_sink, int blocks, int iters, void* stream, double* tflop_per_s);
 
 /* --- Serving: requests are admitted by device-memory footprint and run concurrently on
  *     the device; each request's cells are solved exactly as by camp_solve_device. --- */

@@ -15,7 +15,7 @@ BUILD = os.path.join(PKG, "_build")
 
 HIP_SOURCES = ["api.hip", "engine_wave.hip", "engine_wave_k64a.hip", "engine_wave_k64b.hip",
                "engine_wave_k64c.hip", "engine_wave_k128.hip", "engine_wave_k256.hip",
-               "engine_lane.hip", "autotune.hip", "serve.hip", "noalloc.hip"]
+               "engine_lane.hip", "autotune.hip", "serve.hip", "noalloc.hip", "probe.hip"]
 CXX_SOURCES = ["compile.cpp", "mech_json.cpp", "mech_pack.cpp"]
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-I" + os.path.join(ROOT, "include"), "-I" + CSRC,

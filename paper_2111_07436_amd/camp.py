@@ -75,7 +75,8 @@ class Opts(C.Structure):
                 ("h_min", C.c_double), ("h_init", C.c_double), ("engine", C.c_int),
                 ("wg_per_cu", C.c_int), ("persistent", C.c_int), ("use_graph", C.c_int),
                 ("waves_per_wg", C.c_int), ("stage_tables", C.c_int), ("lanes_per_cell", C.c_int),
-                ("full_newton", C.c_int), ("cell_order", C.c_void_p)]
+                ("full_newton", C.c_int), ("cell_order", C.c_void_p),
+                ("lu_gamma_drift", C.c_double), ("lu_max_age", C.c_int), ("newton_tol", C.c_double)]
 
 
 class CellStats(C.Structure):
@@ -108,6 +109,8 @@ _sig = {
     "camp_lu_factor_device": (C.c_int, [_P, C.c_int, _P, _P]),
     "camp_lu_solve_device": (C.c_int, [_P, C.c_int, _P, _P, _P]),
     "camp_count_failed": (C.c_int, [C.c_int, _P, C.POINTER(C.c_int), _P]),
+    "camp_probe_copy": (C.c_int, [_P, _P, C.c_size_t, C.c_int, _P, C.POINTER(C.c_double)]),
+    "camp_probe_fma": (C.c_int, [_P, C.c_int, C.c_int, _P, C.POINTER(C.c_double)]),
     "camp_plan_create": (C.c_int, [_P, C.c_int, _P, C.POINTER(Env), C.c_double, C.c_double,
                                    C.c_double, C.POINTER(Opts), _P, _P, _P, C.POINTER(_P)]),
     "camp_plan_launch": (C.c_int, [_P, _P]),
@@ -150,7 +153,8 @@ def _stream():
 
 def make_opts(engine="auto", max_order=0, max_steps=0, newton_max_iter=0, h_min=0.0, h_init=0.0,
               wg_per_cu=0, persistent=-1, use_graph=0, waves_per_wg=0, stage_tables=-1,
-              lanes_per_cell=0, full_newton=0, cell_order=None):
+              lanes_per_cell=0, full_newton=0, cell_order=None, lu_gamma_drift=0.0, lu_max_age=0,
+              newton_tol=0.0):
     """camp_opts; ``cell_order`` is an int32 torch tensor (device solves) or numpy array
     (host solves) holding a permutation of the cells, kept alive by the returned object."""
     e = ENGINES[engine] if isinstance(engine, str) else int(engine)
@@ -166,7 +170,8 @@ def make_opts(engine="auto", max_order=0, max_steps=0, newton_max_iter=0, h_min=
                 raise ValueError("cell_order must be a contiguous int32 tensor")
             ptr = cell_order.data_ptr()
     o = Opts(max_order, max_steps, newton_max_iter, h_min, h_init, e, wg_per_cu,
-             persistent, use_graph, waves_per_wg, stage_tables, lanes_per_cell, full_newton, ptr)
+             persistent, use_graph, waves_per_wg, stage_tables, lanes_per_cell, full_newton, ptr,
+             lu_gamma_drift, lu_max_age, newton_tol)
     o._keep = cell_order
     return o
 
@@ -415,6 +420,26 @@ def count_failed(d_status):
     n = C.c_int(0)
     _check(_lib.camp_count_failed(d_status.shape[0], _ptr(d_status), C.byref(n), _stream()))
     return n.value
+
+
+def probe_copy(mib=2048, reps=10):
+    """Sustained device copy bandwidth, GB/s (bytes read plus written)."""
+    import torch
+    n = mib * (1 << 20) // 8
+    a = torch.ones(n, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    v = C.c_double(0)
+    _check(_lib.camp_probe_copy(_ptr(a), _ptr(b), n, reps, _stream(), C.byref(v)))
+    return v.value
+
+
+def probe_fma(blocks=256 * 16, iters=20000):
+    """Sustained FP64 FMA rate, TFLOP/s."""
+    import torch
+    sink = torch.empty(blocks * 256, dtype=torch.float64, device="cuda")
+    v = C.c_double(0)
+    _check(_lib.camp_probe_fma(_ptr(sink), blocks, iters, _stream(), C.byref(v)))
+    return v.value
 
 
 def _host_env(env):

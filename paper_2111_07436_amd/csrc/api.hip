@@ -9,6 +9,7 @@
 #include <vector>
 
 #include "camp.h"
+#include "bdf_common.hpp"
 #include "runtime.hpp"
 
 namespace camp {
@@ -236,7 +237,9 @@ SolveParams make_params(double dt, double rtol, double atol, const camp_opts* o)
   sp.newton_maxit = (o && o->newton_max_iter > 0) ? std::min(o->newton_max_iter, 16) : 4;
   sp.h_min = (o && o->h_min > 0) ? o->h_min : 0.0;
   sp.h_init = (o && o->h_init > 0) ? o->h_init : 0.0;
-  sp.newton_tol = 0.1;
+  sp.newton_tol = (o && o->newton_tol > 0) ? o->newton_tol : kNewtonTol;
+  sp.lu_drift = (o && o->lu_gamma_drift > 0) ? o->lu_gamma_drift : kLuGammaDrift;
+  sp.lu_max_age = (o && o->lu_max_age > 0) ? o->lu_max_age : kLuMaxAge;
   sp.full_newton = (o && o->full_newton) ? 1 : 0;
   sp.order = nullptr;
   sp.order_bad = nullptr;

@@ -19,6 +19,7 @@ constexpr double kMinFactor = 0.2;
 constexpr double kMaxFactor = 5.0;
 constexpr double kLuGammaDrift = 0.3;
 constexpr int kLuMaxAge = 20;
+constexpr double kNewtonTol = 0.1;     // Newton convergence bound in the weighted norm
 constexpr int kMaxConsecFail = 10;
 constexpr double kNewtonDiverge = 2.0;
 // Repeated local-error failures at one step (CVODE's published recovery): from the second

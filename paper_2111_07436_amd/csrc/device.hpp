@@ -84,6 +84,8 @@ struct DevEnv {
 
 struct SolveParams {
   double dt, rtol, atol, h_min, h_init, newton_tol;
+  double lu_drift;    // refactor when gamma drifts by more than this fraction
+  int lu_max_age;     // ... or after this many accepted steps
   double atol_call;   // the caller's atol (a retry attempt may tighten atol)
   int max_order, max_steps, newton_maxit;
   int full_newton;   // 1: full Newton from the start (no Jacobian reuse)

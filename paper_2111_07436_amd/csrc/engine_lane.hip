@@ -339,8 +339,8 @@ __device__ void lane_predict(const LaneCtx& C, int slot, int new_step) {
   }
   const double c_lu = S.c_lu[slot];
   const int need = S.full[slot] || S.force_lu[slot] || !S.lu_valid[slot] ||
-                   fabs(c / c_lu - 1.0) > kLuGammaDrift ||
-                   S.lu_age[slot] >= kLuMaxAge;
+                   fabs(c / c_lu - 1.0) > C.sp.lu_drift ||
+                   S.lu_age[slot] >= C.sp.lu_max_age;
   S.fresh[slot] = need;
   S.lu_ok[slot] = 1;
   S.it[slot] = 0;

@@ -844,7 +844,7 @@ __device__ __forceinline__ int integrate(const DevMech& m, double* yrow, const S
       }
       W.sync();
       int fresh = 0, lu_ok = 1;
-      if (force_lu || !lu_valid || fabs(c / c_lu - 1.0) > kLuGammaDrift || lu_age >= kLuMaxAge) {
+      if (force_lu || !lu_valid || fabs(c / c_lu - 1.0) > sp.lu_drift || lu_age >= sp.lu_max_age) {
         lu_ok = W.newton_matrix_lu(c);
         cs.n_jac++;
         cs.n_lu++;
