@@ -113,7 +113,9 @@ enum {
 typedef struct {
   const char* name;      /* may be NULL                                              */
   int phase;             /* -1 gas, else index into the phase array                  */
-  double mw_kg_mol;      /* gas species: molecular weight (used by phase transfer)   */
+  double mw_kg_mol;      /* gas species: molecular weight (used by phase transfer);  */
+                         /* species of a phase whose radius follows the state: the   */
+                         /* molecular weight that converts moles to particle volume   */
   double diff_m2_s;      /* gas species: gas-phase diffusion coefficient             */
   double accom;          /* gas species: mass accommodation coefficient              */
 } camp_species;
@@ -125,6 +127,15 @@ typedef struct {
   int n_instances;        /* >= 1 (modes, sections or particles)                     */
   double density_kg_m3;   /* > 0                                                     */
   double mw_absorber_kg_mol; /* > 0, SIMPOL absorbing-mass molar mass                */
+  int radius_from_state;  /* 0: particle radius from the environment. 1: the particles */
+                          /* grow with the condensed species (an aerosol representation */
+                          /* computing the radius from particle mass, Sect. 2.2.3): the */
+                          /* environment's radius and mass give the particle core and   */
+                          /* number concentration N_p = m / (rho 4/3 pi r^3), and a     */
+                          /* transfer's rate is evaluated at r(y) = (3 V / (4 pi N_p))^  */
+                          /* (1/3), V = m / rho + sum of y_j MW_j / rho over the phase's  */
+                          /* species (which then need mw_kg_mol > 0). SIMPOL transfer   */
+                          /* only (Henry transfer into such a phase is rejected).       */
 } camp_phase;
 
 typedef struct {

@@ -15,10 +15,26 @@ amount p = c + sum_{j in S} y_j, so r = k prod(y) / p, and by the chain rule
 dr/dy_j = (d mass-action term / dy_j) / p - r / p for j in S (dp/dy_j = 1). A p of exactly 0
 (an instance without absorber or condensed species) gives r = 0.
 
+A transfer into a phase whose particle radius follows the state carries a second
+Parameter, the radius r(y) = (3 V(y) / (4 pi N_p))^(1/3) with the particle volume
+V(y) = V0 + sum_j w_j y_j (w_j = MW_j / rho). Its rate constant, given at the core radius
+r0, is multiplied by psi = r F(lambda / r) / (r0 F(lambda / r0)), the ratio of the
+condensation rates 4 pi r D_g F(Kn) N_p at the two radii (F the Fuchs-Sutugin factor).
+By the chain rule dr/dy_j gains r (d ln psi / dr) w_j / (4 pi N_p r^2) for j in the set,
+with d ln psi / dr = (F(Kn) - Kn F'(Kn)) / (r F(Kn)).
+
 Both are computed densely; the arithmetic works for complex y so that the Jacobian can
 be checked by the complex-step derivative.
 """
 import numpy as np
+
+
+def _fs(Kn, alpha):
+    """Fuchs-Sutugin factor F(Kn) and its derivative dF/dKn."""
+    num = 0.75 * alpha * (1.0 + Kn)
+    den = Kn * Kn + Kn + 0.283 * Kn * alpha + 0.75 * alpha
+    dden = 2.0 * Kn + 1.0 + 0.283 * alpha
+    return num / den, (0.75 * alpha * den - num * dden) / (den * den)
 
 
 class DenseSystem:
@@ -49,13 +65,37 @@ class DenseSystem:
                    np.array(kk, dtype=np.int64), np.array(oo, dtype=np.int64), np.array(cc))
         self.params = [(k, xr.param_const, list(xr.param_species), np.nonzero(S[:, k])[0])
                        for k, xr in enumerate(x.rxns) if xr.param_const >= 0]
+        self.radius = [(k, xr, np.nonzero(S[:, k])[0])
+                       for k, xr in enumerate(x.rxns) if xr.radius_species is not None]
+
+    def radius_terms(self, k, y):
+        """Per radius-parameterized reaction: (psi, d ln psi / dy_j over its species)."""
+        out = {}
+        for kk, xr, _ in self.radius:
+            n_p = k[xr.radius_number]
+            if n_p == 0:
+                out[kk] = (0.0, None)
+                continue
+            v0, lam, a = k[xr.radius_core], k[xr.radius_path], xr.radius_alpha
+            vol = v0 + sum(w * y[j] for j, w in zip(xr.radius_species, xr.radius_weights))
+            r = (3.0 * vol / (4.0 * np.pi * n_p)) ** (1.0 / 3.0)
+            r0 = (3.0 * v0 / (4.0 * np.pi * n_p)) ** (1.0 / 3.0)
+            f, df = _fs(lam / r, a)
+            f0, _ = _fs(lam / r0, a)
+            psi = r * f / (r0 * f0)
+            dlnpsi_dr = (f - (lam / r) * df) / (r * f)
+            drdy = np.array(xr.radius_weights) / (4.0 * np.pi * n_p * r * r)
+            out[kk] = (psi, dlnpsi_dr * drdy)
+        return out
 
     def factors(self, k, y):
-        """Per-reaction parameter factor 1/p (1 for reactions without a parameter)."""
+        """Per-reaction parameter factor: 1/p times psi (1 for reactions without one)."""
         phi = np.ones(len(k), dtype=np.result_type(y, k))
         for kk, d, spec, _ in self.params:
             p = k[d] + sum(y[j] for j in spec)
             phi[kk] = 0.0 if p == 0 else 1.0 / p
+        for kk, (psi, _) in self.radius_terms(k, y).items():
+            phi[kk] = phi[kk] * psi
         return phi
 
     def rates(self, k, y):
@@ -76,11 +116,22 @@ class DenseSystem:
         ii, jj, kk, oo, cc = self.jc
         J = np.zeros((n, n), dtype=np.result_type(y, k))
         np.add.at(J, (ii, jj), cc * (k * phi)[kk] * others[kk, oo])
-        # chain rule through the parameter: dr/dp dp/dy_j = -r phi for every j in its set
-        if self.params:
+        # chain rule through the parameters: dr/dp dp/dy_j = -r / p for every j in the set of
+        # a 1/p factor, and r d ln psi / dy_j for the radius
+        if self.params or self.radius:
             r = self.rates(k, y)
             for kk_, d, spec, members in self.params:
+                p = k[d] + sum(y[j] for j in spec)
+                inv_p = 0.0 if p == 0 else 1.0 / p
                 for i in members:
                     for j in spec:
-                        J[i, j] += self.S[i, kk_] * (-r[kk_] * phi[kk_])
+                        J[i, j] += self.S[i, kk_] * (-r[kk_] * inv_p)
+            rt = self.radius_terms(k, y)
+            for kk_, xr, members in self.radius:
+                psi, dln = rt[kk_]
+                if dln is None:
+                    continue
+                for i in members:
+                    for j, g in zip(xr.radius_species, dln):
+                        J[i, j] += self.S[i, kk_] * r[kk_] * g
         return J

@@ -36,6 +36,11 @@ State concentrations are mol m^-3 of air. Formulas (Table of Process classes):
 * AqueousReversible: K_eq = A exp(C (1/T - 1/298)); reverse rate constant k_r, forward
   K_eq k_r; both act on molarities like an aqueous CondensedPhaseArrhenius rate, so in air
   units k (1000 V)^(1 - n) with n the reactant count of that direction.
+* A phase whose radius follows the state keeps the environment's radius r0 and mass m0 as
+  the particle core: number concentration N_p = m0 / (rho 4/3 pi r0^3) and core volume
+  V0 = m0 / rho (reaction-less entries), and the gas species' mean free path
+  lambda = 3 D_g / c_bar; the transfer rate constants are those at r0, rescaled at every
+  evaluation by the radius Parameter (forcing).
 * An instance with zero phase mass has no particles and no phase volume: every rate
   constant of that instance is 0 (the limit 0 * (1/0) is taken as 0).
 """
@@ -46,7 +51,7 @@ import numpy as np
 from .expand import (K_ARRHENIUS, K_PHOTOLYSIS, K_EMISSION, K_LOSS, K_CONDENSED,
                      K_HENRY_COND, K_HENRY_EVAP, K_SIMPOL_COND, K_SIMPOL_EVAP,
                      K_TROE, K_H2O2, K_OHHNO3, K_TUNNEL, K_AQREV_FWD, K_AQREV_REV,
-                     K_SIMPOL_EVAP_RAOULT, K_ABSORBER)
+                     K_SIMPOL_EVAP_RAOULT, K_ABSORBER, K_NUMBER, K_CORE_VOLUME, K_MEAN_PATH)
 
 AVOGADRO = 6.02214076e23          # mol^-1
 BOLTZMANN = 1.380649e-23          # J K^-1
@@ -111,10 +116,14 @@ def fuchs_sutugin(Kn, alpha):
     return 0.75 * alpha * (1.0 + Kn) / (Kn * Kn + Kn + 0.283 * Kn * alpha + 0.75 * alpha)
 
 
+def mean_free_path(T, diff, mw):
+    """lambda = 3 D_g / c_bar with the mean molecular speed c_bar = sqrt(8 R T / (pi MW))."""
+    return 3.0 * diff / math.sqrt(8.0 * GAS_CONSTANT * T / (math.pi * mw))
+
+
 def condensation_rate(T, radius, number_conc, diff, mw, alpha):
     """First-order condensation rate constant k_c N (s^-1) onto one phase instance."""
-    c_bar = math.sqrt(8.0 * GAS_CONSTANT * T / (math.pi * mw))
-    lam = 3.0 * diff / c_bar
+    lam = mean_free_path(T, diff, mw)
     Kn = lam / radius
     return 4.0 * math.pi * radius * diff * fuchs_sutugin(Kn, alpha) * number_conc
 
@@ -160,6 +169,16 @@ def rate_constants_cell(mech, x, T, P, cos_sza, radius, mass, override=None):
             volume = m / ph.density
             if xr.kind == K_ABSORBER:
                 k[n] = m / ph.mw_absorber
+                continue
+            if xr.kind == K_NUMBER:
+                k[n] = m / (ph.density * (4.0 / 3.0) * math.pi * rad ** 3)
+                continue
+            if xr.kind == K_CORE_VOLUME:
+                k[n] = volume
+                continue
+            if xr.kind == K_MEAN_PATH:
+                gas_sp = mech.species[r.react[0]]
+                k[n] = mean_free_path(T, gas_sp.diff, gas_sp.mw)
                 continue
             if xr.kind in (K_AQREV_FWD, K_AQREV_REV):
                 kk = p[2]

@@ -22,7 +22,7 @@ def structural_pattern(x):
     P = np.eye(n, dtype=bool)
     for xr in x.rxns:
         members = set(xr.react) | set(xr.prod)
-        for j in set(xr.react) | set(xr.param_species or []):
+        for j in set(xr.react) | set(xr.param_species or []) | set(xr.radius_species or []):
             for i in members:
                 P[i, j] = True
     return P

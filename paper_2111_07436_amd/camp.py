@@ -44,7 +44,7 @@ class Species(C.Structure):
 class Phase(C.Structure):
     _fields_ = [("name", C.c_char_p), ("n_species", C.c_int), ("species", C.POINTER(C.c_int)),
                 ("n_instances", C.c_int), ("density_kg_m3", C.c_double),
-                ("mw_absorber_kg_mol", C.c_double)]
+                ("mw_absorber_kg_mol", C.c_double), ("radius_from_state", C.c_int)]
 
 
 class Reaction(C.Structure):
@@ -229,7 +229,8 @@ class Mech:
             self._phase_ids.append(ids)
             nm = p.name.encode()
             self._names.append(nm)
-            ph[i] = Phase(nm, len(p.species), ids, p.n_instances, p.density, p.mw_absorber)
+            ph[i] = Phase(nm, len(p.species), ids, p.n_instances, p.density, p.mw_absorber,
+                          int(getattr(p, "radius_from_state", False)))
         rx = (Reaction * max(1, len(mech.reactions)))()
         for i, r in enumerate(mech.reactions):
             rr = Reaction()

@@ -63,8 +63,9 @@ int upload(camp_mech* mh, int device, DeviceTables& out) {
          o_nr = add(nr.data(), 4 * R), o_v = add(v.data(), 8 * v.size()),
          o_react = add(C.rx_react.data(), 4 * C.rx_react.size()),
          o_pofs = add(C.rx_pofs.data(), 4 * C.rx_pofs.size()),
-         o_rptr = add(C.raoult_ptr.data(), 4 * C.raoult_ptr.size()),
-         o_rao = add(C.raoult.data(), 4 * C.raoult.size()),
+         o_pptr = add(C.param_ptr.data(), 4 * C.param_ptr.size()),
+         o_par = add(C.param.data(), 4 * C.param.size()),
+         o_parw = add(C.param_w.data(), 8 * C.param_w.size()),
          o_tptr = add(C.term_ptr.data(), 4 * C.term_ptr.size()),
          o_trxn = add(C.term_rxn.data(), 4 * C.term_rxn.size()),
          o_tcoef = add(C.term_coef.data(), 8 * C.term_coef.size()),
@@ -113,9 +114,10 @@ int upload(camp_mech* mh, int device, DeviceTables& out) {
   d.rs_v = (const double*)(b + o_v);
   d.rx_react = (const int*)(b + o_react);
   d.rx_pofs = (const int*)(b + o_pofs);
-  d.raoult_ptr = (const int*)(b + o_rptr);
-  d.raoult = (const int*)(b + o_rao);
-  d.n_raoult = (int)C.raoult_ptr.size() - 1;
+  d.param_ptr = (const int*)(b + o_pptr);
+  d.param = (const int*)(b + o_par);
+  d.param_w = (const double*)(b + o_parw);
+  d.n_param = (int)C.param_ptr.size() - 1;
   d.term_ptr = (const int*)(b + o_tptr);
   d.term_rxn = (const int*)(b + o_trxn);
   d.term_coef = (const double*)(b + o_tcoef);
@@ -526,7 +528,7 @@ int camp_mech_load_json(const char* text, camp_mech** out) {
   for (size_t i = 0; i < ph.size(); ++i)
     ph[i] = camp_phase{d.phases[i].name.c_str(), (int)d.phases[i].species.size(),
                        d.phases[i].species.data(), d.phases[i].n_instances, d.phases[i].density,
-                       d.phases[i].mw_absorber};
+                       d.phases[i].mw_absorber, d.phases[i].radius_from_state};
   return camp_mech_load(d.reactions.data(), (int)d.reactions.size(), sp.data(), (int)sp.size(),
                         ph.data(), (int)ph.size(), out);
 }

@@ -343,9 +343,14 @@ std::string compile_mechanism(const camp_reaction* rxns, int n_rxn, const camp_s
     int nr, np;
     int react[3], prod[3];
     double yld[3];
-    // Parameter (full Raoult): the rate is divided by kc[pconst] + sum of y over pspec
-    int pconst = -1;
+    // Parameters (Sect. 2.2.2) over the state indices pspec: kParamRaoult divides the rate by
+    // kc[pconst] + sum of y; kParamRadius evaluates the transfer rate at the radius grown by
+    // sum of pw * y (entries pnum, pcore, ppath; accommodation palpha)
+    int pflags = 0;
+    int pconst = -1, pnum = -1, pcore = -1, ppath = -1;
+    double palpha = 0.0;
     std::vector<int> pspec;
+    std::vector<double> pw;
   };
   std::vector<X> xs;
   std::vector<RateSpec> rs;
@@ -594,6 +599,21 @@ std::string compile_mechanism(const camp_reaction* rxns, int n_rxn, const camp_s
       }
       const bool henry = t == CAMP_RXN_HENRY_TRANSFER;
       const bool raoult = !henry && q.p[4] != 0.0;
+      const bool grows = ph[p].radius_from_state != 0;
+      if (grows && henry) {
+        err << "reaction " << r << ": Henry transfer into a phase whose radius follows the state "
+                                   "is not supported";
+        return err.str();
+      }
+      if (grows)
+        for (int m = 0; m < ph[p].n_species; ++m) {
+          const double mw = sp[ph[p].species[m]].mw_kg_mol;
+          if (!(mw > 0) || !finite(mw)) {
+            err << "reaction " << r << ": species of a phase whose radius follows the state need a "
+                                       "positive molecular weight";
+            return err.str();
+          }
+        }
       if (!henry && q.p[4] != 0.0 && q.p[4] != 1.0) {
         err << "reaction " << r << ": SIMPOL full-Raoult flag p[4] must be 0 or 1";
         return err.str();
@@ -603,6 +623,10 @@ std::string compile_mechanism(const camp_reaction* rxns, int n_rxn, const camp_s
         return err.str();
       }
       for (int i = 0; i < ph[p].n_instances; ++i) {
+        // entries pushed after the two directions: [absorber], [number, core volume, path]
+        const int after = (int)xs.size() + 2;
+        const int absorber = raoult ? after : -1;
+        const int geo = after + (raoult ? 1 : 0);
         for (int dir = 0; dir < 2; ++dir) {
           RateSpec s = base_spec(henry ? (dir == 0 ? KR_HENRY_COND : KR_HENRY_EVAP)
                                        : (dir == 0 ? KR_SIMPOL_COND
@@ -622,25 +646,42 @@ std::string compile_mechanism(const camp_reaction* rxns, int n_rxn, const camp_s
           x.react[0] = dir == 0 ? gs : as;
           x.prod[0] = dir == 0 ? as : gs;
           x.yld[0] = 1.0;
-          if (raoult && dir == 1) {
-            // total condensed amount of the instance: the absorber entry pushed next plus
-            // every species of the phase
-            x.pconst = (int)xs.size() + 1;
+          if ((raoult && dir == 1) || grows)
             for (int m = 0; m < ph[p].n_species; ++m)
               x.pspec.push_back(cond_state(p, i, ph[p].species[m]));
+          if (raoult && dir == 1) {
+            // total condensed amount of the instance: the absorber entry plus every species
+            x.pflags |= kParamRaoult;
+            x.pconst = absorber;
+          }
+          if (grows) {
+            x.pflags |= kParamRadius;
+            x.pnum = geo;
+            x.pcore = geo + 1;
+            x.ppath = geo + 2;
+            x.palpha = g.accom;
+            for (int m = 0; m < ph[p].n_species; ++m)
+              x.pw.push_back(sp[ph[p].species[m]].mw_kg_mol / ph[p].density_kg_m3);
           }
           xs.push_back(x);
           rs.push_back(s);
         }
-        if (raoult) {
-          RateSpec s = base_spec(KR_ABSORBER);
+        auto carrier = [&](int kind) {
+          RateSpec s = base_spec(kind);
           s.inst = phase_first_inst[p] + i;
+          s.v[0] = g.diff_m2_s;
+          s.v[1] = g.mw_kg_mol;
           s.v[3] = ph[p].density_kg_m3;
           s.v[4] = ph[p].mw_absorber_kg_mol;
           s.nr = 0;
-          X x{};
-          xs.push_back(x);
+          xs.push_back(X{});
           rs.push_back(s);
+        };
+        if (raoult) carrier(KR_ABSORBER);
+        if (grows) {
+          carrier(KR_NUMBER);
+          carrier(KR_CORE_VOLUME);
+          carrier(KR_MEAN_PATH);
         }
       }
     } else {
@@ -690,7 +731,7 @@ std::string compile_mechanism(const camp_reaction* rxns, int n_rxn, const camp_s
     long long nnz = 0, n_part = 0;
     for (int i = 0; i < N; ++i)
       for (int j = 0; j < N; ++j) nnz += F.get(i, j);
-    for (const X& x : xs) n_part += x.nr + (x.pconst >= 0 ? 1 : 0);
+    for (const X& x : xs) n_part += x.nr + n_param_partials(x.pflags);
     // Gauss-Jordan keeps 4K doubles in the partials / rates scratch of a cell
     const int scratch_k = (int)(std::max<long long>(n_part, (long long)xs.size()) / 4);
     C.nnz_lu = (int)nnz;
@@ -727,18 +768,29 @@ std::string compile_mechanism(const camp_reaction* rxns, int n_rxn, const camp_s
   for (int k = 0; k < R; ++k) {
     C.rx_nr[k] = xs[k].nr;
     for (int o = 0; o < xs[k].nr; ++o) C.rx_react[3 * k + o] = C.iperm[xs[k].react[o]];
-    // a reaction with a parameter has one more partial: dr/dp dp/dy_j, equal for every j
-    C.rx_pofs[k + 1] = C.rx_pofs[k] + xs[k].nr + (xs[k].pconst >= 0 ? 1 : 0);
+    // each Parameter adds one partial after the reactant occurrences: -r / p for the 1/p
+    // factor (equal for every j of the set), r dln(psi)/dr / (4 pi N_p r^2) for the radius
+    // (times w_j in the Jacobian contributions)
+    C.rx_pofs[k + 1] = C.rx_pofs[k] + xs[k].nr + n_param_partials(xs[k].pflags);
   }
   C.n_partials = C.rx_pofs[R];
-  C.raoult_ptr.assign(1, 0);
-  C.raoult.clear();
+  C.param_ptr.assign(1, 0);
+  C.param.clear();
+  C.param_w.clear();
   for (int k = 0; k < R; ++k) {
-    if (xs[k].pconst < 0) continue;
-    C.raoult.push_back(k);
-    C.raoult.push_back(xs[k].pconst);
-    for (int j : xs[k].pspec) C.raoult.push_back(C.iperm[j]);
-    C.raoult_ptr.push_back((int)C.raoult.size());
+    const X& x = xs[k];
+    if (!x.pflags) continue;
+    const int rec[kParamHead] = {k, x.pflags, x.pconst, x.pnum, x.pcore, x.ppath};
+    for (int v : rec) {
+      C.param.push_back(v);
+      C.param_w.push_back(0.0);
+    }
+    C.param_w[C.param_w.size() - kParamHead + 1] = x.palpha;
+    for (size_t j = 0; j < x.pspec.size(); ++j) {
+      C.param.push_back(C.iperm[x.pspec[j]]);
+      C.param_w.push_back(x.pw.empty() ? 0.0 : x.pw[j]);
+    }
+    C.param_ptr.push_back((int)C.param.size());
   }
 
   // forcing terms by species (elimination position), reactions ascending
@@ -768,14 +820,21 @@ std::string compile_mechanism(const camp_reaction* rxns, int n_rxn, const camp_s
           by[s].push_back({C.rx_pofs[k] + o, e.second});
         }
       }
-    for (int k = 0; k < R; ++k)
-      for (int jj : xs[k].pspec) {
-        int j = C.iperm[jj];
-        for (auto& e : members[k]) {
-          if (e.second == 0.0) continue;
-          by[slot(C.iperm[e.first], j)].push_back({C.rx_pofs[k] + xs[k].nr, e.second});
+    for (int k = 0; k < R; ++k) {
+      int part = C.rx_pofs[k] + xs[k].nr;
+      for (int flag : {kParamRaoult, kParamRadius}) {
+        if (!(xs[k].pflags & flag)) continue;
+        for (size_t jj = 0; jj < xs[k].pspec.size(); ++jj) {
+          const int j = C.iperm[xs[k].pspec[jj]];
+          const double w = flag == kParamRadius ? xs[k].pw[jj] : 1.0;
+          for (auto& e : members[k]) {
+            if (e.second == 0.0) continue;
+            by[slot(C.iperm[e.first], j)].push_back({part, e.second * w});
+          }
         }
+        ++part;
       }
+    }
     C.jc_ptr.assign(C.nnz + 1, 0);
     for (int s = 0; s < C.nnz; ++s) {
       for (auto& e : by[s]) {

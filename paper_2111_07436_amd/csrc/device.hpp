@@ -43,10 +43,12 @@ struct DevMech {
   // reactions
   const int* rx_react;         // [R * 3], -1 padded, elimination positions
   const int* rx_pofs;          // [R + 1]
-  // reactions with a Parameter (full Raoult): records {k, d, s_1 .. s_m}, see Compiled
-  const int* raoult_ptr;       // [n_raoult + 1]
-  const int* raoult;
-  int n_raoult;
+  // reactions with Parameters: records {k, flags, d, dN, dV, dL, s_1 .. s_m} and their
+  // weights at the same positions, see Compiled
+  const int* param_ptr;        // [n_param + 1]
+  const int* param;
+  const double* param_w;
+  int n_param;
   // forcing terms per species
   const int* term_ptr;
   const int* term_rxn;
@@ -165,6 +167,7 @@ __device__ inline double rate_constant(const DevMech& m, int r, double T, double
   const double ms = mass[g];
   if (ms == 0.0) return 0.0;
   if (kind == 17) return ms / v[4];  // absorbing moles of the instance
+  if (kind == 19) return ms / v[3];  // particle core volume per volume of air
   if (kind == 14 || kind == 15) {  // aqueous reversible: forward K k_r, reverse k_r, on molarities
     const int nr = m.rs_nr[r];
     const double vol = ms / v[3];
@@ -188,9 +191,11 @@ __device__ inline double rate_constant(const DevMech& m, int r, double T, double
   const double rad = radius[g];
   const double Dg = v[0], mw = v[1], alpha = v[2], rho = v[3];
   const double c_bar = sqrt(8.0 * kGasConstant * T / (kPi * mw));
+  if (kind == 20) return 3.0 * Dg / c_bar;   // mean free path
   const double Kn = 3.0 * Dg / c_bar / rad;
   const double ffs = 0.75 * alpha * (1.0 + Kn) / (Kn * Kn + Kn + 0.283 * Kn * alpha + 0.75 * alpha);
   const double n_part = ms / (rho * (4.0 / 3.0) * kPi * rad * rad * rad);
+  if (kind == 18) return n_part;             // particle number concentration
   const double kc = 4.0 * kPi * rad * Dg * ffs * n_part;
   if (kind == 6 || kind == 8) return kc;
   if (kind == 7) {  // Henry evaporation
@@ -205,17 +210,56 @@ __device__ inline double rate_constant(const DevMech& m, int r, double T, double
   return kc * p0 * kAtmPa / (kGasConstant * T * n_abs);
 }
 
-// Factor 1/p of parameter record q (reaction k = its first entry): p = kc(d) plus the sum of
-// the state over the record's species, summed in record order; 0 when p = 0 (an instance
-// with neither absorber nor condensed mass).
+// Fuchs-Sutugin factor F(Kn) and its derivative.
+__device__ __forceinline__ void fuchs_sutugin(double Kn, double alpha, double& f, double& df) {
+  const double num = 0.75 * alpha * (1.0 + Kn);
+  const double den = Kn * Kn + Kn + 0.283 * Kn * alpha + 0.75 * alpha;
+  const double dden = 2.0 * Kn + 1.0 + 0.283 * alpha;
+  f = num / den;
+  df = (0.75 * alpha * den - num * dden) / (den * den);
+}
+
+// The Parameters of record q (reaction k = its first entry): the rate factor phi (1/p and
+// psi multiplied), and the chain-rule factors inv_p = 1/p and g = dln(psi)/dr /
+// (4 pi N_p r^2) (see Compiled::param). Sums run in record order.
+struct ParamEval {
+  int k, flags;
+  double phi, inv_p, g;
+};
 template <class Kc, class Y>
-__device__ __forceinline__ double parameter_factor(const DevMech& m, int q, int& k, Kc kc, Y y) {
-  const int b = m.raoult_ptr[q], e = m.raoult_ptr[q + 1];
-  k = m.raoult[b];
-  double s = 0.0;
-  for (int i = b + 2; i < e; ++i) s += y(m.raoult[i]);
-  const double p = kc(m.raoult[b + 1]) + s;
-  return p != 0.0 ? 1.0 / p : 0.0;
+__device__ __forceinline__ ParamEval parameter_eval(const DevMech& m, int q, Kc kc, Y y) {
+  const int b = m.param_ptr[q], e = m.param_ptr[q + 1];
+  ParamEval r;
+  r.k = m.param[b];
+  r.flags = m.param[b + 1];
+  r.phi = 1.0;
+  r.inv_p = 0.0;
+  r.g = 0.0;
+  if (r.flags & 1) {
+    double s = 0.0;
+    for (int i = b + 6; i < e; ++i) s += y(m.param[i]);
+    const double p = kc(m.param[b + 2]) + s;
+    r.inv_p = p != 0.0 ? 1.0 / p : 0.0;
+    r.phi = r.inv_p;
+  }
+  if (r.flags & 2) {
+    const double np = kc(m.param[b + 3]);
+    if (np == 0.0) {
+      r.phi = 0.0;
+    } else {
+      double s = 0.0;
+      for (int i = b + 6; i < e; ++i) s += m.param_w[i] * y(m.param[i]);
+      const double v0 = kc(m.param[b + 4]), lam = kc(m.param[b + 5]), alpha = m.param_w[b + 1];
+      const double scale = 3.0 / (4.0 * kPi * np);
+      const double rad = cbrt(scale * (v0 + s)), rad0 = cbrt(scale * v0);
+      double f, df, f0, df0;
+      fuchs_sutugin(lam / rad, alpha, f, df);
+      fuchs_sutugin(lam / rad0, alpha, f0, df0);
+      r.phi *= rad * f / (rad0 * f0);
+      r.g = (f - (lam / rad) * df) / (rad * f) / (4.0 * kPi * np * rad * rad);
+    }
+  }
+  return r;
 }
 
 // Moves a double between lanes with one DPP pattern (both 32-bit halves).

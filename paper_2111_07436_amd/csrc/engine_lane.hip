@@ -74,11 +74,10 @@ struct Lane {
       if (c >= 0) r *= y(c);
       P(k) = r;
     }
-    for (int q = 0; q < m.n_raoult; ++q) {   // rates with a parameter: r = kc prod(y) / p
-      int k;
-      const double phi = parameter_factor(m, q, k, [&](int d) { return kc(d); },
+    for (int q = 0; q < m.n_param; ++q) {   // rates with Parameters: r = kc prod(y) phi(y)
+      const ParamEval pe = parameter_eval(m, q, [&](int d) { return kc(d); },
                                           [&](int j) { return y(j); });
-      P(k) *= phi;
+      P(pe.k) *= pe.phi;
     }
     int ok = 1;
     for (int t = 0; t < m.N; ++t) {
@@ -101,14 +100,14 @@ struct Lane {
       if (b >= 0) P(base + 1) = kk * ya * yc;
       if (cc >= 0) P(base + 2) = kk * ya * yb;
     }
-    for (int q = 0; q < m.n_raoult; ++q) {   // chain rule through the parameter p
-      int k;
-      const double phi = parameter_factor(m, q, k, [&](int d) { return kc(d); },
+    for (int q = 0; q < m.n_param; ++q) {   // chain rule through the Parameters
+      const ParamEval pe = parameter_eval(m, q, [&](int d) { return kc(d); },
                                           [&](int j) { return y(j); });
-      const int o = m.rx_pofs[k];
-      const double r = kc(k) * y(m.rx_react[3 * k]) * phi;
-      P(o) = kc(k) * phi;
-      P(o + 1) = -r * phi;
+      int o = m.rx_pofs[pe.k];
+      const double r = kc(pe.k) * y(m.rx_react[3 * pe.k]) * pe.phi;
+      P(o++) = kc(pe.k) * pe.phi;
+      if (pe.flags & 1) P(o++) = -r * pe.inv_p;
+      if (pe.flags & 2) P(o) = r * pe.g;
     }
     for (int s = 0; s < m.Z; ++s) {
       double acc = 0.0;

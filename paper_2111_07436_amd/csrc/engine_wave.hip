@@ -26,7 +26,7 @@ int wave_resident_cells_per_cu(int n_state, int mode, int lanes) {
   return 4 * per_simd / (lanes / 64);
 }
 
-int wave_effective_mode(const DevMech& m, int mode) { return m.n_raoult ? kParamMode : mode; }
+int wave_effective_mode(const DevMech& m, int mode) { return m.n_param ? kParamMode : mode; }
 
 size_t wave_cell_bytes(const DevMech& m) { return sizeof(double) * cell_doubles(m, 0); }
 
@@ -47,7 +47,7 @@ hipError_t launch_bdf_wave(const DevMech& m, const DevEnv& env, double* state, i
   if (!wave_lanes_ok(m.N, lanes)) return hipErrorInvalidValue;
   if (stage < 0 || (stage > 4 && stage != kParamMode)) return hipErrorInvalidValue;
   stage = wave_effective_mode(m, stage);
-  if (stage == kParamMode && !m.n_raoult) return hipErrorInvalidValue;
+  if (stage == kParamMode && !m.n_param) return hipErrorInvalidValue;
   const StageView& view = m.sv[lanes / 128];
   if (!view.base || view.wave_lists != lanes / kWave) return hipErrorInvalidValue;
   if (waves < 1 || waves > wave_max_waves(m.N, stage, lanes)) return hipErrorInvalidValue;
@@ -162,11 +162,11 @@ hipError_t launch_wave_step(const DevMech& m, int op, int n_cells, const double*
   if (n_cells == 0) return hipSuccess;
 #define CAMP_STEP_CASE(K)                                                                      \
   case K: {                                                                                    \
-    const void* fn = m.n_raoult ? (const void*)wave_step_kernel<K, true>                       \
+    const void* fn = m.n_param ? (const void*)wave_step_kernel<K, true>                       \
                                 : (const void*)wave_step_kernel<K, false>;                     \
     hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds); \
     if (e != hipSuccess) return e;                                                             \
-    if (m.n_raoult)                                                                            \
+    if (m.n_param)                                                                            \
       hipLaunchKernelGGL((wave_step_kernel<K, true>), dim3(n_cells), dim3(kWave), lds, stream, \
                          m, op, n_cells, kin, yin, out, gamma);                                \
     else                                                                                       \

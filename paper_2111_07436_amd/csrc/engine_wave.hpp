@@ -368,13 +368,12 @@ struct WaveCell {
                   [&](const TermEntry& t, const double (&y)[3]) {
                     P[t.x] = t.c * yfac(t.e, 0, y[0]) * yfac(t.e, 1, y[1]) * yfac(t.e, 2, y[2]);
                   });
-    if constexpr (kPar) {   // rates with a parameter: r = kc prod(y) / p
+    if constexpr (kPar) {   // rates with Parameters: r = kc prod(y) phi(y)
       sync();
-      for (int q = lane; q < m.n_raoult; q += G) {
-        int k;
-        const double phi = parameter_factor(m, q, k, [&](int d) { return kc[d]; },
+      for (int q = lane; q < m.n_param; q += G) {
+        const ParamEval pe = parameter_eval(m, q, [&](int d) { return kc[d]; },
                                             [&](int j) { return yl[j]; });
-        P[k] *= phi;
+        P[pe.k] *= pe.phi;
       }
     }
     for (int t = lane; t < m.N; t += G) xl[t] = 0.0;
@@ -408,15 +407,15 @@ struct WaveCell {
                   });
     for (int s = lane; s < m.Z; s += G) M[s] = 0.0;
     sync();
-    if constexpr (kPar) {   // chain rule through the parameter p: kc / p and -r / p
-      for (int q = lane; q < m.n_raoult; q += G) {
-        int k;
-        const double phi = parameter_factor(m, q, k, [&](int d) { return kc[d]; },
+    if constexpr (kPar) {   // chain rule through the Parameters (one reactant each)
+      for (int q = lane; q < m.n_param; q += G) {
+        const ParamEval pe = parameter_eval(m, q, [&](int d) { return kc[d]; },
                                             [&](int j) { return yl[j]; });
-        const int o = m.rx_pofs[k];
-        const double r = kc[k] * yl[m.rx_react[3 * k]] * phi;
-        P[o] = kc[k] * phi;
-        P[o + 1] = -r * phi;
+        int o = m.rx_pofs[pe.k];
+        const double r = kc[pe.k] * yl[m.rx_react[3 * pe.k]] * pe.phi;
+        P[o++] = kc[pe.k] * pe.phi;
+        if (pe.flags & 1) P[o++] = -r * pe.inv_p;
+        if (pe.flags & 2) P[o] = r * pe.g;
       }
       sync();
     }

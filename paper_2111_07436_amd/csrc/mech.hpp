@@ -29,8 +29,19 @@ enum RateKind : int {
   KR_AQREV_FWD = 14,
   KR_AQREV_REV = 15,
   KR_SIMPOL_EVAP_RAOULT = 16,
-  KR_ABSORBER = 17
+  KR_ABSORBER = 17,
+  KR_NUMBER = 18,
+  KR_CORE_VOLUME = 19,
+  KR_MEAN_PATH = 20
 };
+
+// Parameter flags of a reaction (Sect. 2.2.2), and the fixed head of its record.
+constexpr int kParamRaoult = 1;   // rate divided by p = kc[d] + sum of y over the set
+constexpr int kParamRadius = 2;   // transfer rate at the radius grown by the set's volume
+constexpr int kParamHead = 6;     // {k, flags, d, dN, dV, dL}
+inline int n_param_partials(int flags) {
+  return ((flags & kParamRaoult) ? 1 : 0) + ((flags & kParamRadius) ? 1 : 0);
+}
 
 constexpr int kRateParams = 12;
 
@@ -48,6 +59,9 @@ constexpr int kRateParams = 12;
 //                  rate's parameter supplies (the instance's total condensed moles)
 //   ABSORBER  : v[3] = density, v[4] = mw_absorber; no reactants or products, rate
 //                  constant m / mw_absorber (the absorbing moles of one phase instance)
+//   NUMBER, CORE_VOLUME, MEAN_PATH: carriers of a phase whose radius follows the state:
+//                  particle number concentration m / (rho 4/3 pi r^3), core volume m / rho,
+//                  the gas species' mean free path 3 D_g / c_bar (v[0] = D_g, v[1] = MW_g)
 struct RateSpec {
   int kind;
   int ext;    // column of rate_override, or -1
@@ -86,12 +100,19 @@ struct Compiled {
   std::vector<int> rx_nr;               // [R]
   std::vector<int> rx_pofs;             // [R + 1] partial offsets
   int n_partials = 0;
-  // Reactions with a Parameter (Sect. 2.2.2): record q in [raoult_ptr[q], raoult_ptr[q+1])
-  // of `raoult` holds {k, d, s_1 .. s_m}: reaction k's rate is divided by
-  // p = kc[d] + y[s_1] + .. + y[s_m] (elimination positions), with r = 0 when p = 0. Its
-  // partials are P[rx_pofs[k]] = kc[k] / p (the reactant occurrence) and
-  // P[rx_pofs[k] + 1] = -r / p (the chain rule through p, shared by every s_j).
-  std::vector<int> raoult_ptr{0}, raoult;
+  // Reactions with Parameters (Sect. 2.2.2), one record per reaction: `param` in
+  // [param_ptr[q], param_ptr[q+1]) holds {k, flags, d, dN, dV, dL, s_1 .. s_m} (state
+  // indices as elimination positions) and `param_w` at the same positions holds the
+  // accommodation coefficient (at the flags slot) and the weights w_j = MW_j / rho (at the
+  // s_j slots). Reaction k's rate is multiplied by
+  //   1 / p, p = kc[d] + sum_j y[s_j]           (kParamRaoult; 0 when p = 0), and
+  //   psi = r F(kc[dL] / r) / (r0 F(kc[dL] / r0)), r = (3 V / (4 pi kc[dN]))^(1/3),
+  //   V = kc[dV] + sum_j w_j y[s_j], r0 the radius at V = kc[dV]   (kParamRadius; F the
+  //   Fuchs-Sutugin factor; 0 when kc[dN] = 0).
+  // Partials: P[rx_pofs[k]] = kc[k] psi / p for the reactant occurrence, then -r / p and
+  // r dln(psi)/dr / (4 pi kc[dN] r^2), one per Parameter in that order.
+  std::vector<int> param_ptr{0}, param;
+  std::vector<double> param_w;
 
   // forcing: f_t = sum_q term_coef[q] * r[term_rxn[q]], q in [term_ptr[t], term_ptr[t+1])
   std::vector<int> term_ptr, term_rxn;
@@ -204,6 +225,7 @@ struct MechDescription {
     std::vector<int> species;
     int n_instances = 1;
     double density = 1000.0, mw_absorber = 0.2;
+    int radius_from_state = 0;
   };
   std::vector<Species> species;
   std::vector<Phase> phases;

@@ -9,7 +9,8 @@
 //                   "diffusion coeff [m2 s-1]": 1.5e-5, "accommodation coefficient": 0.1},
 //                  {"name": "P1_org", "phase": "organic"}, ... ],
 //   "phases":    [ {"name": "organic", "species": ["P1_org", ...], "density [kg m-3]": 1400,
-//                   "absorber molecular weight [kg mol-1]": 0.2}, ... ],
+//                   "absorber molecular weight [kg mol-1]": 0.2,
+//                   "radius from state": false}, ... ],
 //   "aerosol representation": {"type": "sections", "instances": {"organic": 8, ...}},
 //   "processes": [ {"type": "ARRHENIUS", "reactants": {"O3": 1, "NO": 1},
 //                   "products": {"NO2": 1.0}, "A": 3e-12, "Ea/kb [K]": 1500}, ... ]
@@ -247,9 +248,12 @@ std::string parse_mechanism_json(const char* text, size_t len, MechDescription& 
       if (ni && ni->kind == JVal::NUM) n = ni->num;
       if (!(n >= 1.0) || n != std::floor(n)) return "JSON: phase \"" + nm->str + "\" needs a positive integer instance count";
       x.n_instances = (int)n;
+      double grows = 0.0;
       if (!number(q, "density [kg m-3]", 1000.0, &x.density) ||
-          !number(q, "absorber molecular weight [kg mol-1]", 0.2, &x.mw_absorber))
+          !number(q, "absorber molecular weight [kg mol-1]", 0.2, &x.mw_absorber) ||
+          !number(q, "radius from state", 0.0, &grows))
         return "JSON: phase \"" + nm->str + "\" has a non-numeric property";
+      x.radius_from_state = grows != 0.0 ? 1 : 0;
       out.phases.push_back(x);
     }
   }

@@ -16,7 +16,7 @@ namespace camp {
 namespace {
 
 constexpr char kMagic[8] = {'C', 'A', 'M', 'P', 'M', 'E', 'C', 'H'};
-constexpr uint32_t kVersion = 3;
+constexpr uint32_t kVersion = 4;
 
 uint64_t fnv1a(const uint8_t* p, size_t n) {
   uint64_t h = 1469598103934665603ull;
@@ -70,7 +70,7 @@ void fields(IO& io, C& c, S* stage) {
   io.pod(c.n_partials);
   io.vec(c.inst_phase); io.vec(c.inst_base); io.vec(c.perm); io.vec(c.iperm);
   io.vec(c.rate); io.vec(c.rx_react); io.vec(c.rx_nr); io.vec(c.rx_pofs);
-  io.vec(c.raoult_ptr); io.vec(c.raoult);
+  io.vec(c.param_ptr); io.vec(c.param); io.vec(c.param_w);
   io.vec(c.term_ptr); io.vec(c.term_rxn); io.vec(c.term_coef);
   io.vec(c.row_ptr); io.vec(c.col); io.vec(c.diag); io.vec(c.pattern0);
   io.vec(c.jc_ptr); io.vec(c.jc_part); io.vec(c.jc_coef);
@@ -127,15 +127,23 @@ std::string unpack_compiled(const uint8_t* buf, size_t size, Compiled& C, StageB
       (int)C.col.size() != C.nnz || (int)C.diag.size() != C.n_state || (int)C.rate.size() != C.n_rxn ||
       (int)C.rx_react.size() != 3 * C.n_rxn || (int)C.rx_pofs.size() != C.n_rxn + 1)
     return "packed mechanism is inconsistent";
-  if (C.raoult_ptr.empty() || C.raoult_ptr[0] != 0 || C.raoult_ptr.back() != (int)C.raoult.size())
+  if (C.param_ptr.empty() || C.param_ptr[0] != 0 || C.param_ptr.back() != (int)C.param.size() ||
+      C.param_w.size() != C.param.size())
     return "packed mechanism is inconsistent";
-  for (size_t q = 0; q + 1 < C.raoult_ptr.size(); ++q) {
-    const int b = C.raoult_ptr[q], e = C.raoult_ptr[q + 1];
-    if (e < b + 2) return "packed mechanism is inconsistent";
-    if (C.raoult[b] < 0 || C.raoult[b] >= C.n_rxn || C.raoult[b + 1] < 0 || C.raoult[b + 1] >= C.n_rxn)
+  for (size_t q = 0; q + 1 < C.param_ptr.size(); ++q) {
+    const int b = C.param_ptr[q], e = C.param_ptr[q + 1];
+    if (e < b + kParamHead || b < 0) return "packed mechanism is inconsistent";
+    const int k = C.param[b], fl = C.param[b + 1];
+    if (k < 0 || k >= C.n_rxn || fl < 1 || fl > 3) return "packed mechanism is inconsistent";
+    for (int i = 2; i < kParamHead; ++i) {
+      const int d = C.param[b + i];
+      const bool used = (i == 2) ? (fl & kParamRaoult) : (fl & kParamRadius);
+      if (used && (d < 0 || d >= C.n_rxn)) return "packed mechanism is inconsistent";
+    }
+    if (C.rx_nr[k] != 1 || C.rx_pofs[k + 1] - C.rx_pofs[k] != 1 + n_param_partials(fl))
       return "packed mechanism is inconsistent";
-    for (int i = b + 2; i < e; ++i)
-      if (C.raoult[i] < 0 || C.raoult[i] >= C.n_state) return "packed mechanism is inconsistent";
+    for (int i = b + kParamHead; i < e; ++i)
+      if (C.param[i] < 0 || C.param[i] >= C.n_state) return "packed mechanism is inconsistent";
   }
   for (int v = 0; v < 4; ++v) {
     const StageBlock& s = stage[v];

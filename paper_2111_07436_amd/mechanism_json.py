@@ -28,10 +28,15 @@ def to_dict(mech: W.Mechanism) -> dict:
         if s.phase < 0:
             e.update({"molecular weight [kg mol-1]": s.mw, "diffusion coeff [m2 s-1]": s.diff,
                       "accommodation coefficient": s.accom})
+        elif getattr(mech.phases[s.phase], "radius_from_state", False):
+            e["molecular weight [kg mol-1]"] = s.mw
         species.append(e)
     phases = [{"name": ph.name, "species": [names[i] for i in ph.species],
                "density [kg m-3]": ph.density, "absorber molecular weight [kg mol-1]": ph.mw_absorber}
               for ph in mech.phases]
+    for e, ph in zip(phases, mech.phases):
+        if getattr(ph, "radius_from_state", False):
+            e["radius from state"] = True
     procs = []
     for r in mech.reactions:
         p = list(r.p) + [0.0] * (10 - len(r.p))

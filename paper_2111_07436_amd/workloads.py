@@ -63,6 +63,7 @@ class Phase:
     n_instances: int
     density: float = 1400.0         # kg m^-3
     mw_absorber: float = 0.2        # kg mol^-1 (SIMPOL absorbing-mass molar mass)
+    radius_from_state: bool = False  # particle radius grows with the condensed species
 
 
 @dataclass
@@ -400,7 +401,8 @@ def gen_rate_type_zoo(rng) -> Mechanism:
     emission, first-order loss, Troe fall-off, HO2 self-reaction, OH + HNO3, tunneling, and
     an aqueous phase of 3 instances with Henry's-law and SIMPOL transfer, condensed-phase
     Arrhenius and reversible reactions, and an organic phase of 2 instances whose SIMPOL
-    partitioning takes the full Raoult mole fraction (a state-dependent Parameter).
+    partitioning takes the full Raoult mole fraction and whose particles grow with the
+    condensed species (two state-dependent Parameters).
     Parameters are drawn from ranges typical of tropospheric kinetics (pre-exponential
     factors in molecule cm^-3 units)."""
     lu = lambda lo, hi: float(np.exp(rng.uniform(np.log(lo), np.log(hi))))
@@ -408,12 +410,13 @@ def gen_rate_type_zoo(rng) -> Mechanism:
                  diff=float(rng.uniform(0.8e-5, 2.0e-5)), accom=float(rng.uniform(0.05, 0.5)))
          for i in range(12)]
     aq = [Species(name=f"AQ{i}", phase=0) for i in range(5)]
-    org = [Species(name=f"ORG{i}", phase=1) for i in range(3)]
+    org = [Species(name=f"ORG{i}", phase=1, mw=0.15 + 0.05 * i) for i in range(3)]
     species = g + aq + org
     A0, A1, A2, A3, A4 = 12, 13, 14, 15, 16
     O0, O1, O2 = 17, 18, 19
     phases = [Phase("aqueous", [A0, A1, A2, A3, A4], 3, density=1000.0, mw_absorber=0.1),
-              Phase("organic", [O0, O1, O2], 2, density=1200.0, mw_absorber=0.25)]
+              Phase("organic", [O0, O1, O2], 2, density=1200.0, mw_absorber=0.25,
+                    radius_from_state=True)]
 
     def arr3():
         return [lu(1e-13, 1e-11), float(rng.uniform(-600.0, 600.0)), float(rng.uniform(-1.5, 0.0))]

@@ -106,6 +106,17 @@ def test_validation_errors():
     # phase without instances / species
     _expect_einval(W.Mechanism(sp, [W.Phase("p", [1, 2], 0)], []))
     _expect_einval(W.Mechanism(sp[:1], [W.Phase("p", [], 1)], []))
+    # a phase whose radius follows the state: no Henry transfer, species need a molecular weight
+    grow = [W.Phase("p", [1, 2], 2, radius_from_state=True)]
+    _expect_einval(W.Mechanism(sp, grow, [W.Reaction(W.RXN_HENRY_TRANSFER, [0], [1], [1.0],
+                                                     [1.0, 0, 0, 0, 0, 0], phase=0)]))
+    simpol = W.Reaction(W.RXN_SIMPOL_TRANSFER, [0], [1], [1.0], [3000.0, -20.0, 0, 0, 1.0, 0], phase=0)
+    sp0 = [W.Species("G", -1), W.Species("A", 0), W.Species("B", 0, mw=0.0)]
+    _expect_einval(W.Mechanism(sp0, grow, [simpol]))
+    camp.Mech(W.Mechanism(sp, grow, [simpol]))   # accepted with molecular weights
+    # the full-Raoult flag is 0 or 1
+    bad_flag = W.Reaction(W.RXN_SIMPOL_TRANSFER, [0], [1], [1.0], [3000.0, -20.0, 0, 0, 0.5, 0], phase=0)
+    _expect_einval(W.Mechanism(sp, [W.Phase("p", [1, 2], 2)], [bad_flag]))
 
 
 def test_cell_order_must_be_a_permutation():
