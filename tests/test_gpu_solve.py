@@ -394,3 +394,12 @@ def test_c5_sample_against_stored_oracle(torch):
         log(f"c5 sample: {len(cells)} cells, {kw}")
         y = gpu_solve(m, sub, **kw)
         assert_parity(y, ref, what=f"c5/{kw}")
+
+
+def test_peak_probes(torch):
+    from paper_2111_07436_amd import camp
+    gbs = camp.probe_copy(mib=512, reps=4)
+    tf = camp.probe_fma(blocks=1024, iters=2000)
+    log(f"copy {gbs:.0f} GB/s, FP64 FMA {tf:.1f} TFLOP/s")
+    assert 500.0 < gbs < 8000.0 * 1.05    # below the published HBM peak
+    assert 1.0 < tf < 78.6 * 1.05         # below the published FP64 vector peak

@@ -139,3 +139,16 @@ def test_schedule_counts_consistent():
     assert inf["lu_pairs"] > 0 and inf["lu_levels"] > 0
     assert inf["fwd_levels"] > 0 and inf["bwd_levels"] > 0
     assert inf["n_partials"] >= 0 and inf["n_terms"] > 0 and inf["n_jac_contrib"] > 0
+
+
+def test_probes_reject_bad_arguments():
+    """The measurement probes validate their arguments before any device call."""
+    import ctypes
+    v = ctypes.c_double(0)
+    lib = camp._lib
+    assert lib.camp_probe_copy(None, None, 1024, 1, None, ctypes.byref(v)) == camp.EINVAL
+    buf = (ctypes.c_double * 4)()
+    assert lib.camp_probe_copy(buf, buf, 3, 1, None, ctypes.byref(v)) == camp.EINVAL   # odd n
+    assert lib.camp_probe_copy(buf, buf, 4, 0, None, ctypes.byref(v)) == camp.EINVAL   # no reps
+    assert lib.camp_probe_fma(None, 1, 1, None, ctypes.byref(v)) == camp.EINVAL
+    assert lib.camp_probe_fma(buf, 0, 1, None, ctypes.byref(v)) == camp.EINVAL
