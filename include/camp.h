@@ -317,8 +317,12 @@ typedef struct {
   int steps, rejected, newton_fail, newton_iters, n_f, n_jac, n_lu, order;
 } camp_cell_stats;
 
-/* Solve n_cells cells with host arrays. state[cells][n_state] is read and overwritten in
- * place. cell_status[cells] and cell_stats[cells] may be NULL. opts may be NULL.
+/* Solve n_cells cells with host arrays (paper Sect. 2.4.2, runtime workflow: the host
+ * model hands over the environment and concentrations of each grid cell, the solver
+ * integrates the chemistry over the host time step, the new state is read back; Sect.
+ * 2.4.1: each cell by variable-order BDF with Newton iteration and error control).
+ * state[cells][n_state] is read and overwritten in place. cell_status[cells] and
+ * cell_stats[cells] may be NULL. opts may be NULL.
  * Returns CAMP_ESOLVE if any cell failed (its row is left at its input values). */
 int camp_solve(camp_mech* mech, int n_cells, double* state, const camp_env* env, double dt,
                double rtol, double atol, const camp_opts* opts, int* cell_status,
@@ -421,7 +425,9 @@ int camp_probe_copy(const double* d_src, double* d_dst, size_t n, int reps, void
 int camp_probe_fma(double* d_sink, int blocks, int iters, void* stream, double* tflop_per_s);
 
 /* --- Serving: requests are admitted by device-memory footprint and run concurrently on
- *     the device; each request's cells are solved exactly as by camp_solve_device. --- */
+ *     the device; each request's cells are solved exactly as by camp_solve_device. Several
+ *     mechanisms may be resident at once, one compiled object each (paper Sect. 2.1: one
+ *     core object per mechanism, several serving different mechanisms). --- */
 typedef struct camp_server camp_server;
 
 /* max_bytes: budget of device memory for in-flight requests (0 = 50% of free memory). A
