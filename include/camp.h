@@ -179,8 +179,10 @@ int camp_mech_pack(const camp_mech* mech, void* buf, size_t capacity, size_t* si
 
 /* Rebuild a mechanism from camp_mech_pack's buffer (same library format version). The
  * buffer is checked for magic, version, length and checksum and its tables for internal
- * consistency; a buffer from any other source is rejected with CAMP_EINVAL. The caller may
- * free buf on return. Device tables upload on first use, as for camp_mech_load. */
+ * consistency; a buffer from any other source is rejected with CAMP_EINVAL. The checksum
+ * guards against accidental damage, not against a buffer crafted to pass it: the contents
+ * of the index tables are trusted. The caller may free buf on return. Device tables upload
+ * on first use, as for camp_mech_load. */
 int camp_mech_unpack(const void* buf, size_t size, camp_mech** out);
 
 typedef struct {
