@@ -287,8 +287,10 @@ struct WaveCell {
   // Terms per lane issued together in the LU and sweep levels: levels of large mechanisms
   // hold several terms per lane, small ones rarely more than one.
   static constexpr int kLevelBatch = NPL >= 4 ? 4 : 1;
-  // Levels whose first table entries are read together (sweeps, LU).
-  static constexpr int kWindow = (G == kWave && NPL <= 2) ? 2 : 8;
+  // Levels whose first table entries are read together (sweeps, LU). Measured: the
+  // one-wavefront kernels of up to three species per lane and the four-wavefront kernels
+  // are fastest with short windows (registers are tight there), the others with 8.
+  static constexpr int kWindow = (G == kWave && NPL <= 3) ? 2 : G == 4 * kWave ? 3 : 8;
   // Dense-tail entries per lane (see tail_invert; max_tail bounds K to fit).
   static constexpr int kTail = G == kWave ? kTailPerLaneOneWave : kTailPerLane;
   // Product terms per lane issued together beyond a level's first (registers are tightest

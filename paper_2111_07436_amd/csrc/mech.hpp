@@ -199,7 +199,7 @@ struct StageBlock {
 // i = w, w + W, ...; its lanes are split into max(1, 64 / K) groups of K lanes, lane j of a
 // group owning column j of every group-th row; a lane holds at most kTailPerLane entries.
 // It also needs 4K doubles of scratch.
-constexpr int kTailPerLane = 12;
+constexpr int kTailPerLane = 10;
 constexpr int kTailPerLaneOneWave = 4;   // one wavefront per cell: registers are tighter
 int max_tail(int wave_lists);
 
