@@ -64,8 +64,8 @@ PLAIN_CELLS_EQUAL = 8192
 KERNEL_SOURCES = ["paper_2111_07436_amd/csrc/engine_wave.hpp", "paper_2111_07436_amd/csrc/device.hpp",
                   "paper_2111_07436_amd/csrc/bdf_common.hpp", "paper_2111_07436_amd/csrc/compile.cpp"]
 MEASURED_TRAFFIC = {
-    "c5": {"fetch_kib": 56696948.2, "fetch_scale": 1.999924, "write_kib": 18740009.0, "write_scale": 1.000000, "sources": "391bc072afb2f0d0"},
-    "c2": {"fetch_kib": 1254814.6, "fetch_scale": 1.999924, "write_kib": 1329922.6, "write_scale": 1.000000, "sources": "391bc072afb2f0d0"},
+    "c5": {"fetch_kib": 280991953.6, "fetch_scale": 1.999925, "write_kib": 19070278.8, "write_scale": 1.000000, "sources": "32f166085a84ad10"},
+    "c2": {"fetch_kib": 1259698.5, "fetch_scale": 1.999925, "write_kib": 1329652.7, "write_scale": 1.000000, "sources": "32f166085a84ad10"},
 }
 
 
