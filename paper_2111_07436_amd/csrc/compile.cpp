@@ -186,11 +186,11 @@ std::vector<int> choose_order(int n, const std::vector<std::pair<int, int>>& edg
 // the head rows, Crout levels where tail entries sum over head pivots only.
 struct TailCost {
   int fwd = 0, bwd = 0, lu = 0;
-  // Measured on the fused kernel (cycles of one group): a sweep level costs about a third of
-  // an LU level, a Gauss-Jordan step about a quarter, and one LU serves about seven Newton
-  // iterations; weights per iteration: sweep level 7, LU level 3, Gauss-Jordan step 1, plus
-  // one sweep level for the product with the inverse.
-  long long weight(int K) const { return 7LL * (fwd + bwd + (K ? 1 : 0)) + 3LL * lu + (K ? K + 1 : 0); }
+  // Measured on the fused kernel (cycles of one group): a sweep level costs about half an
+  // LU level, a Gauss-Jordan step about as much as an LU level, and one factorization serves
+  // about seven Newton iterations; weights per factorization interval: sweep level 7, LU level
+  // 3, Gauss-Jordan step 3, plus one sweep level for the product with the inverse.
+  long long weight(int K) const { return 7LL * (fwd + bwd + (K ? 1 : 0)) + 3LL * lu + (K ? 3LL * (K + 1) : 0); }
 };
 
 TailCost tail_cost(int n, const Bits& F, int K) {
