@@ -62,10 +62,11 @@ PLAIN_CELLS_EQUAL = 8192
 # the kernel and table-compiler sources it was taken with (their SHA-256 prefix); otherwise
 # reported null.
 KERNEL_SOURCES = ["paper_2111_07436_amd/csrc/engine_wave.hpp", "paper_2111_07436_amd/csrc/device.hpp",
-                  "paper_2111_07436_amd/csrc/bdf_common.hpp", "paper_2111_07436_amd/csrc/compile.cpp"]
+                  "paper_2111_07436_amd/csrc/bdf_common.hpp", "paper_2111_07436_amd/csrc/compile.cpp",
+                  "paper_2111_07436_amd/csrc/mech.hpp", "paper_2111_07436_amd/csrc/engine_wave.hip"]
 MEASURED_TRAFFIC = {
-    "c5": {"fetch_kib": 280991953.6, "fetch_scale": 1.999925, "write_kib": 19070278.8, "write_scale": 1.000000, "sources": "32f166085a84ad10"},
-    "c2": {"fetch_kib": 1259698.5, "fetch_scale": 1.999925, "write_kib": 1329652.7, "write_scale": 1.000000, "sources": "32f166085a84ad10"},
+    "c5": {"fetch_kib": 284296741.6, "fetch_scale": 1.999924, "write_kib": 19119394.3, "write_scale": 1.000000, "sources": "ee0ad744c69bedb7"},
+    "c2": {"fetch_kib": 1259305.8, "fetch_scale": 1.999924, "write_kib": 1330889.9, "write_scale": 1.000000, "sources": "ee0ad744c69bedb7"},
 }
 
 
