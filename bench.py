@@ -33,7 +33,7 @@ sys.path.insert(0, ROOT)
 METRIC = "cell-steps/sec at rtol 1e-4 vs plain per-cell BDF; served p50/p99 latency"
 HBM_PEAK_GBS = 8000.0              # MI355X HBM3E
 FP64_VECTOR_PEAK_TFLOPS = 78.6     # MI355X FP64 vector (256 CU x 2.4 GHz x 128 flop/clk)
-CPU_SHARE = 16                     # host cores the GPU machine allots to one GPU
+CPU_SHARE = 16                     # host cores allotted to one GPU
 
 WORKLOADS = {
     "c1": "plain box model: 100 cells, 20 species / 40 reactions, 60 x 60 s",
@@ -426,7 +426,7 @@ def cpu_baseline(wl, rtol, atol, sample):
                       f"core; failed cells are not counted",
             "seconds": dt, "failed": int(len(cells) - ok), "host_nproc": os.cpu_count(),
             "host_cpu": cpu_model(),
-            "cores_note": f"the GPU box allots {CPU_SHARE} host cores to one GPU"}
+            "cores_note": f"{CPU_SHARE} host cores are allotted to one GPU"}
 
 
 # ---------------------------------------------------------------- main
