@@ -65,8 +65,8 @@ KERNEL_SOURCES = ["paper_2111_07436_amd/csrc/engine_wave.hpp", "paper_2111_07436
                   "paper_2111_07436_amd/csrc/bdf_common.hpp", "paper_2111_07436_amd/csrc/compile.cpp",
                   "paper_2111_07436_amd/csrc/mech.hpp", "paper_2111_07436_amd/csrc/engine_wave.hip"]
 MEASURED_TRAFFIC = {
-    "c5": {"fetch_kib": 10238426.4, "fetch_scale": 1.999926, "write_kib": 12313547.8, "write_scale": 1.000000, "sources": "f7759217c8bc8065"},
-    "c2": {"fetch_kib": 1259406.4, "fetch_scale": 1.999926, "write_kib": 1328677.8, "write_scale": 1.000000, "sources": "f7759217c8bc8065"},
+    "c5": {"fetch_kib": 10242521.5, "fetch_scale": 1.999925, "write_kib": 12309663.2, "write_scale": 1.000000, "sources": "1b9a7952ee5dfb37"},
+    "c2": {"fetch_kib": 1260731.6, "fetch_scale": 1.999925, "write_kib": 1329192.6, "write_scale": 1.000000, "sources": "1b9a7952ee5dfb37"},
 }
 
 

@@ -294,10 +294,10 @@ struct WaveCell {
   // Dense-tail entries per lane (see tail_invert; max_tail bounds K to fit).
   static constexpr int kTail = G == kWave ? kTailPerLaneOneWave : kTailPerLane;
   // Product terms per lane issued together beyond a level's first. Measured: 2 where
-  // registers are tightest (the one-wavefront kernels of at most two species per lane, and
-  // the four-wavefront kernels: 2 % faster on 520 state variables than 4, while 1 and 8
-  // are slower); kTermBatch elsewhere.
-  static constexpr int kProdBatch = ((G == kWave && NPL <= 2) || G == 4 * kWave) ? 2 : kTermBatch;
+  // registers are tightest (the one-wavefront kernels of at most three species per lane,
+  // 2 % faster than 4 on 192 state variables, and the four-wavefront kernels, 2 % faster
+  // on 520 state variables, where 1 and 8 are slower); kTermBatch elsewhere.
+  static constexpr int kProdBatch = ((G == kWave && NPL <= 3) || G == 4 * kWave) ? 2 : kTermBatch;
   const DevMech& m;
   Tabs tb;
   double* M;
